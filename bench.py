@@ -1,0 +1,236 @@
+"""Benchmark: hybrid CSR+BCSR SpMM forward + backward on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload stencil|gcn|powerlaw]
+
+A step is one pass of the whole path over one batch of synthetic input with
+everything resident in HBM: C = A B, dB = A^T dC and dA = SDDMM(dC, B) on
+A's pattern (the plan is built once, outside the timed region, as the paper
+excludes format conversion from its SpMM timing).  Default workload: the
+65,536 x 65,536 block stencil (128 x 128 grid, 4 DOFs, 9-point, dense 4x4
+couplings, +5 % scattered entries; 2,451,523 stored entries), dense width
+N = 128, FP32.
+
+Prints one JSON line: GFLOP/s of the hybrid (AUTO split) step counting
+6 nnz N flops (2 nnz N per product, Table 3's convention), the same for the
+CSR-only path, the error of every output against the FP64 oracle, the
+roofline entry of the dominant kernel (HIP events on the launch stream) and
+the oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="stencil", choices=["stencil", "gcn", "powerlaw"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted((ROOT / "paper_2511_08158_amd" / "csrc").iterdir()):
+        h.update(p.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def workload(name):
+    import gen
+    if name == "stencil":
+        a, b = gen.config2()
+        return a, b, "f32", "block_stencil_65536_n128"
+    if name == "gcn":
+        a, b = gen.config4()
+        return a, b, "f32", "gcn_232965_n128"
+    a, b = gen.config3(n=64)
+    return a, b, "f16", "powerlaw_1048576_n64"
+
+
+def alg_bytes_forward(m, k, nnz, n, sv, sb, sc):
+    """Compulsory HBM bytes of one product: A once (index + value per entry,
+    row pointer), the dense input once, the output once."""
+    return nnz * (sv + 4) + 4 * (m + 1) + k * n * sb + m * n * sc
+
+
+def alg_bytes_sddmm(m, k, nnz, n, sb, sg, sd):
+    return nnz * 4 + 4 * (m + 1) + m * n * sg + k * n * sb + nnz * sd
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "this build has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2511_08158_amd as hs
+
+    dev = torch.device("cuda:0")
+    a, b, dt, wname = workload(args.workload)
+    tdtype = {"f32": torch.float32, "f16": torch.float16}[dt]
+    n = b.shape[1]
+    g = gen.dense(0, gen.GRAD, a.m, n)
+    vals = torch.tensor(a.vals, device=dev)
+    B = torch.tensor(b, device=dev).to(tdtype)
+    dC = torch.tensor(g, device=dev, dtype=torch.float32)
+
+    def make(split):
+        t0 = time.perf_counter()
+        p = hs.Plan(a.row_ptr, a.col_idx, vals, (a.m, a.k), compute=tdtype, split=split,
+                    backward=True, n_hint=n)
+        torch.cuda.synchronize()
+        return p, (time.perf_counter() - t0) * 1e3
+
+    stream = torch.cuda.current_stream()
+
+    def time_steps(plan, steps, warmup):
+        C = torch.empty((a.m, n), dtype=torch.float32, device=dev)
+        for _ in range(warmup):
+            plan.run(B, out=C)
+            plan.backward(B, dC)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.run(B, out=C)
+            plan.backward(B, dC)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    def time_kernels(plan, reps):
+        """Average duration of each launch, HIP events on the launch stream."""
+        C = torch.empty((a.m, n), dtype=torch.float32, device=dev)
+        out = {}
+        calls = {
+            "forward": lambda: plan.run(B, out=C),
+            "backward_dB": lambda: plan.backward(B, dC, need_dB=True, need_dA=False),
+            "backward_dA": lambda: plan.backward(B, dC, need_dB=False, need_dA=True),
+        }
+        for name, fn in calls.items():
+            for _ in range(3):
+                fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out[name] = e0.elapsed_time(e1) / reps * 1e3  # us
+        return out
+
+    results = {}
+    for split in ("auto", "csr"):
+        plan, plan_ms = make(split)
+        t = time_steps(plan, args.steps, args.warmup)
+        kt = time_kernels(plan, max(10, args.steps))
+        results[split] = {"plan": plan, "t": t, "plan_ms": plan_ms, "kernels_us": kt,
+                          "info": plan.info()}
+
+    # errors of the hybrid outputs against the FP64 oracle
+    import oracle
+    hyb = results["auto"]["plan"]
+    C = hyb.run(B)
+    dB, dA = hyb.backward(B, dC)
+    torch.cuda.synchronize()
+    b_used = B.double().cpu().numpy()
+    ref_c = oracle.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, b_used)
+    ref_db = oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, g)
+    ref_da = oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, g, b_used)
+    err = {"C": oracle.rel_err(C.double().cpu().numpy(), ref_c),
+           "dB": oracle.rel_err(dB.double().cpu().numpy(), ref_db),
+           "dA": oracle.rel_err(dA.double().cpu().numpy(), ref_da)}
+    tol = 1e-5 if dt == "f32" else 5e-3
+
+    flops = 6.0 * a.nnz * n
+    t_h, t_c = results["auto"]["t"], results["csr"]["t"]
+    gflops = flops / t_h / 1e9
+
+    # roofline of the dominant kernel of the hybrid step
+    sv = sb = 4 if dt == "f32" else 2
+    per_launch = {
+        "forward": alg_bytes_forward(a.m, a.k, a.nnz, n, sv, sb, 4),
+        "backward_dB": alg_bytes_forward(a.k, a.m, a.nnz, n, 4, 4, 4),
+        "backward_dA": alg_bytes_sddmm(a.m, a.k, a.nnz, n, sb, 4, 4),
+    }
+    kt = results["auto"]["kernels_us"]
+    dom = max(kt, key=kt.get)
+    achieved = per_launch[dom] / (kt[dom] * 1e-6) / 1e9
+    traffic = None
+    prof = ROOT / "profiles" / f"traffic_{wname}.json"
+    if prof.exists():
+        rec = json.loads(prof.read_text())
+        if rec.get("sources_hash") == kernel_sources_hash():
+            traffic = rec.get("bytes_per_launch", {}).get(dom)
+    step_bytes = sum(per_launch.values())
+
+    line = {
+        "metric": "SpMM GFLOP/s & % HBM roofline, hybrid vs CSR-only, fwd+bwd, at stated error",
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_h * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dt,
+        "data": "synthetic",
+        "config": {"workload": wname, "m": a.m, "k": a.k, "nnz": a.nnz, "n": n,
+                   "step": "C=A*B; dB=A^T*dC; dA=SDDMM(dC,B)", "split": "auto"},
+        "hbm_roofline_frac_step": round(step_bytes / t_h / (HBM_PEAK_GBS * 1e9), 4),
+        "csr_only": {"value": round(flops / t_c / 1e9, 2), "ms_per_step": round(t_c * 1e3, 5),
+                     "kernels_us": {k: round(v, 2) for k, v in results["csr"]["kernels_us"].items()}},
+        "speedup_vs_csr_only": round(t_c / t_h, 3),
+        "error": {k: float(f"{v:.3e}") for k, v in err.items()},
+        "error_ok": all(v <= tol for v in err.values()),
+        "kernels_us": {k: round(v, 2) for k, v in kt.items()},
+        "plan_ms": round(results["auto"]["plan_ms"], 1),
+        "split": {k: results["auto"]["info"][k] for k in ("rows_csr", "rb_bcsr", "nblk", "fill")},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "alg_bytes_per_launch": per_launch[dom]},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle as orc
+        threads = len(os.sched_getaffinity(0))
+        threads = min(threads, 16)
+        # bounded sample: whole fwd+bwd passes of the oracle on the same
+        # workload until about --cpu-seconds of CPU work has run
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            orc.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, b_used, nthreads=threads)
+            orc.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, g, nthreads=threads)
+            orc.sddmm(a.m, a.k, a.row_ptr, a.col_idx, g, b_used, nthreads=threads)
+            reps += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds or reps >= 50:
+                break
+        tc = (time.perf_counter() - t0) / reps
+        line["cpu_baseline"] = {"value": round(flops / tc / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
+                                "kind": "oracle",
+                                "sample": f"{reps} full fwd+bwd passes of the FP64 oracle on the same workload"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

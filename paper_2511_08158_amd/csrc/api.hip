@@ -1,0 +1,313 @@
+// C ABI of the hspmm library (include/hspmm.h).
+#include <algorithm>
+#include <chrono>
+#include <new>
+
+#include "plan.h"
+
+struct hspmm_plan {
+    hspmm::Plan p;
+};
+
+namespace hspmm {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+void clear_error() { g_last_error.clear(); }
+
+int fail(int code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what, const char* file, int line) {
+    std::string m = std::string("HIP error ") + hipGetErrorString(e) + " in " + what + " (" + file + ":" +
+                    std::to_string(line) + ")";
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return fail(HSPMM_ERR_OOM, m);
+    return fail(HSPMM_ERR_HIP, m);
+}
+
+void DevBuf::release() {
+    if (ptr) {
+        (void)hipFree(ptr);
+        if (owner) owner->in_use -= bytes;
+    }
+    ptr = nullptr;
+    bytes = 0;
+    owner = nullptr;
+}
+
+int Allocator::alloc(DevBuf& b, size_t nbytes) {
+    b.release();
+    if (nbytes == 0) nbytes = 4;
+    if (limit && in_use + nbytes > limit)
+        return fail(HSPMM_ERR_OOM, "plan exceeds max_workspace_bytes (" + std::to_string(limit) + ")");
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HSPMM_ERR_OOM, std::string("hipMalloc of ") + std::to_string(nbytes) +
+                                       " bytes failed: " + hipGetErrorString(e));
+    }
+    b.ptr = p;
+    b.bytes = nbytes;
+    b.owner = this;
+    in_use += nbytes;
+    peak = std::max(peak, in_use);
+    return HSPMM_OK;
+}
+
+int ensure_ws(Plan& p, size_t bytes) {
+    if (bytes <= p.ws.bytes) return HSPMM_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    return p.al.alloc(p.ws, bytes);
+}
+
+}  // namespace hspmm
+
+using namespace hspmm;
+
+namespace {
+
+int check_opts(const hspmm_plan_opts* o, hspmm_plan_opts* out) {
+    hspmm_plan_opts d{};
+    d.struct_size = sizeof(hspmm_plan_opts);
+    d.compute = HSPMM_F32;
+    d.split = HSPMM_SPLIT_AUTO;
+    d.block_rows = 16;
+    d.r_boundary = -1;
+    d.n_hint = 128;
+    d.want_backward = 0;
+    d.max_workspace_bytes = 0;
+    if (o) {
+        if (o->struct_size != sizeof(hspmm_plan_opts))
+            return fail(HSPMM_ERR_ARG, "hspmm_plan_opts.struct_size mismatch");
+        d = *o;
+        if (d.block_rows == 0) d.block_rows = 16;
+        if (d.n_hint <= 0) d.n_hint = 128;
+    }
+    if (!dtype_valid(d.compute)) return fail(HSPMM_ERR_DTYPE, "unsupported compute dtype");
+    if (d.split < HSPMM_SPLIT_AUTO || d.split > HSPMM_SPLIT_BOUNDARY) return fail(HSPMM_ERR_ARG, "bad split mode");
+    if (d.block_rows != 16) return fail(HSPMM_ERR_ARG, "block_rows must be 16 (the MFMA tile height)");
+    *out = d;
+    return HSPMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hybrid_spmm_plan(hspmm_plan_t* out, int64_t m, int64_t k, int64_t nnz, const int32_t* row_ptr,
+                     const int32_t* col_idx, const void* vals, int32_t vals_dtype, const hspmm_plan_opts* opts,
+                     void* stream) {
+    clear_error();
+    if (!out) return fail(HSPMM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (m < 0 || k < 0 || nnz < 0) return fail(HSPMM_ERR_ARG, "negative dimension");
+    if (m >= (int64_t(1) << 31) - 1 || k >= (int64_t(1) << 31) - 1 || nnz >= (int64_t(1) << 31) - 1)
+        return fail(HSPMM_ERR_OVERFLOW, "m, k and nnz must be below 2^31 - 1");
+    if (!row_ptr) return fail(HSPMM_ERR_ARG, "row_ptr is NULL");
+    if (nnz > 0 && (!col_idx || !vals)) return fail(HSPMM_ERR_ARG, "col_idx or vals is NULL");
+    if (!dtype_valid(vals_dtype)) return fail(HSPMM_ERR_DTYPE, "unsupported vals dtype");
+    if (nnz > 0 && k == 0) return fail(HSPMM_ERR_CSR, "entries in a matrix with no columns");
+    hspmm_plan_opts o;
+    int rc = check_opts(opts, &o);
+    if (rc) return rc;
+    const auto t0 = std::chrono::steady_clock::now();
+    hspmm_plan* h = new (std::nothrow) hspmm_plan();
+    if (!h) return fail(HSPMM_ERR_OOM, "host allocation failed");
+    Plan& p = h->p;
+    p.opts = o;
+    p.compute = o.compute;
+    p.m = m;
+    p.k = k;
+    p.nnz_in = nnz;
+    p.br = o.block_rows;
+    p.al.limit = o.max_workspace_bytes;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = build_plan(p, row_ptr, col_idx, vals, vals_dtype, s);
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        delete h;
+        return rc;
+    }
+    p.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return HSPMM_OK;
+}
+
+int hybrid_spmm_run(hspmm_plan_t h, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc, void* stream) {
+    clear_error();
+    if (!h) return fail(HSPMM_ERR_ARG, "plan is NULL");
+    Plan& p = h->p;
+    if (n < 0) return fail(HSPMM_ERR_ARG, "n < 0");
+    if (n == 0 || p.m == 0) return HSPMM_OK;
+    if (!C) return fail(HSPMM_ERR_ARG, "C is NULL");
+    if (p.k > 0 && !B) return fail(HSPMM_ERR_ARG, "B is NULL");
+    if (ldc < n || (p.k > 0 && ldb < n)) return fail(HSPMM_ERR_ARG, "leading dimension smaller than n");
+    return launch_forward(p, p.A, n, B, ldb, C, ldc, static_cast<hipStream_t>(stream));
+}
+
+int hybrid_spmm_backward(hspmm_plan_t h, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc,
+                         void* dB, int64_t lddb, void* dA_vals, void* stream) {
+    clear_error();
+    if (!h) return fail(HSPMM_ERR_ARG, "plan is NULL");
+    Plan& p = h->p;
+    if (n < 0) return fail(HSPMM_ERR_ARG, "n < 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dB) {
+        if (!p.has_T) return fail(HSPMM_ERR_NO_BACKWARD, "plan was built without want_backward");
+        if (n > 0 && p.k > 0) {
+            if (lddb < n || (p.m > 0 && lddc < n)) return fail(HSPMM_ERR_ARG, "leading dimension smaller than n");
+            if (p.m > 0 && !dC) return fail(HSPMM_ERR_ARG, "dC is NULL");
+            HSPMM_TRY(launch_forward(p, p.T, n, dC, lddc, dB, lddb, s));
+        }
+    }
+    if (dA_vals && p.nnz_in > 0) {
+        if (n > 0 && (!B || !dC)) return fail(HSPMM_ERR_ARG, "B or dC is NULL");
+        if (n > 0 && (ldb < n || lddc < n)) return fail(HSPMM_ERR_ARG, "leading dimension smaller than n");
+        HSPMM_TRY(launch_sddmm(p, n, B, ldb, dC, lddc, dA_vals, s));
+    }
+    return HSPMM_OK;
+}
+
+int hybrid_spmm_update_values(hspmm_plan_t h, const void* vals, int32_t vals_dtype, void* stream) {
+    clear_error();
+    if (!h) return fail(HSPMM_ERR_ARG, "plan is NULL");
+    if (!dtype_valid(vals_dtype)) return fail(HSPMM_ERR_DTYPE, "unsupported vals dtype");
+    Plan& p = h->p;
+    if (p.nnz_in > 0 && !vals) return fail(HSPMM_ERR_ARG, "vals is NULL");
+    return pack_values(p, vals, vals_dtype, static_cast<hipStream_t>(stream));
+}
+
+int hybrid_spmm_plan_info(hspmm_plan_t h, hspmm_plan_info* info) {
+    clear_error();
+    if (!h || !info) return fail(HSPMM_ERR_ARG, "NULL argument");
+    if (info->struct_size != sizeof(hspmm_plan_info)) return fail(HSPMM_ERR_ARG, "hspmm_plan_info.struct_size mismatch");
+    const Plan& p = h->p;
+    hspmm_plan_info i{};
+    i.struct_size = sizeof(hspmm_plan_info);
+    i.compute = p.compute;
+    i.m = p.m;
+    i.k = p.k;
+    i.nnz_input = p.nnz_in;
+    i.nnz = p.nnz;
+    i.block_rows = p.br;
+    i.canonical_input = p.canonical ? 1 : 0;
+    i.rows_csr = p.A.rows_csr;
+    i.nnz_csr = p.A.nnz_csr;
+    i.long_rows = p.A.n_long;
+    i.rb_bcsr = p.A.rb_bcsr;
+    i.nblk = p.A.nblk;
+    i.nblk_padded = p.A.nblk_pad;
+    i.nnz_bcsr = p.A.nnz_bcsr;
+    i.fill = p.A.nblk ? (double)p.A.nnz_bcsr / ((double)p.A.nblk * p.br) : 0.0;
+    i.pred_us_csr = p.A.pred_csr * 1e6;
+    i.pred_us_bcsr = p.A.pred_bcsr * 1e6;
+    i.r_boundary = p.A.r_boundary;
+    i.bytes_device = (int64_t)p.al.in_use;
+    i.plan_ms = p.plan_ms;
+    i.has_backward = p.has_T ? 1 : 0;
+    i.t_rows_csr = p.T.rows_csr;
+    i.t_rb_bcsr = p.T.rb_bcsr;
+    i.t_nblk = p.T.nblk;
+    *info = i;
+    return HSPMM_OK;
+}
+
+int hybrid_spmm_export(hspmm_plan_t h, int32_t which, int32_t field, void* dst, int64_t capacity, int64_t* bytes) {
+    clear_error();
+    if (!h || !bytes) return fail(HSPMM_ERR_ARG, "NULL argument");
+    Plan& p = h->p;
+    if (which != 0 && which != 1) return fail(HSPMM_ERR_ARG, "which must be 0 (A) or 1 (A^T)");
+    if (which == 1 && !p.has_T) return fail(HSPMM_ERR_NO_BACKWARD, "no transposed plan");
+    SubPlan& X = which ? p.T : p.A;
+    const bool half = X.ct == HSPMM_F16 || X.ct == HSPMM_BF16;
+    const size_t ev = dtype_size(X.ct);
+    std::vector<uint8_t> buf;
+    auto put_i32 = [&](const std::vector<int32_t>& v) {
+        buf.resize(v.size() * 4);
+        if (!v.empty()) memcpy(buf.data(), v.data(), buf.size());
+    };
+    auto fetch = [&](const DevBuf& d, size_t nb, std::vector<uint8_t>& out) -> int {
+        out.resize(nb);
+        if (nb) HIP_TRY(hipMemcpy(out.data(), d.ptr, nb, hipMemcpyDeviceToHost));
+        return HSPMM_OK;
+    };
+    switch (field) {
+        case HSPMM_F_RB_CLASS: {
+            std::vector<int32_t> v(X.h_cls.begin(), X.h_cls.end());
+            put_i32(v);
+            break;
+        }
+        case HSPMM_F_RB_NNZ: put_i32(X.h_rb_nnz); break;
+        case HSPMM_F_RB_NBLK: put_i32(X.h_rb_nblk); break;
+        case HSPMM_F_CSR_ROWS: HSPMM_TRY(fetch(X.csr_rows, X.rows_csr * 4, buf)); break;
+        case HSPMM_F_CSR_PTR: HSPMM_TRY(fetch(X.csr_ptr, (X.rows_csr + 1) * 4, buf)); break;
+        case HSPMM_F_CSR_COL: HSPMM_TRY(fetch(X.csr_col, X.nnz_csr * 4, buf)); break;
+        case HSPMM_F_CSR_VAL: HSPMM_TRY(fetch(X.csr_val, X.nnz_csr * ev, buf)); break;
+        case HSPMM_F_BCSR_RB: put_i32(X.h_bcsr_rb); break;
+        case HSPMM_F_BLK_PTR: {
+            std::vector<int32_t> v(1, 0);
+            for (int32_t c : X.h_blk_cnt) v.push_back(v.back() + c);
+            put_i32(v);
+            break;
+        }
+        case HSPMM_F_BLK_COL:
+        case HSPMM_F_BLK_VAL: {
+            std::vector<uint8_t> raw;
+            const bool val = field == HSPMM_F_BLK_VAL;
+            HSPMM_TRY(fetch(val ? X.blk_val : X.blk_col, (size_t)X.nblk_pad * (val ? 16 * ev : 4), raw));
+            const size_t per = val ? 16 * ev : 4;
+            buf.resize((size_t)X.nblk * per);
+            size_t o = 0;
+            for (size_t sl = 0; sl < X.h_blk_cnt.size(); ++sl) {
+                for (int32_t b = 0; b < X.h_blk_cnt[sl]; ++b) {
+                    const int64_t blk = (int64_t)X.h_blk_ptr[sl] + b;
+                    if (!val) {
+                        memcpy(buf.data() + o, raw.data() + blk * 4, 4);
+                        o += 4;
+                    } else {
+                        for (int i = 0; i < 16; ++i) {
+                            const int64_t pi = half ? (blk >> 5) * 512 + ((blk & 31) >> 3) * 128 + i * 8 + (blk & 7)
+                                                    : blk * 16 + i;
+                            memcpy(buf.data() + o, raw.data() + pi * ev, ev);
+                            o += ev;
+                        }
+                    }
+                }
+            }
+            break;
+        }
+        case HSPMM_F_RB_SCALE: {
+            if (X.scaled) {
+                HSPMM_TRY(fetch(X.scale, X.nrb * 8, buf));
+            } else {
+                std::vector<double> one((size_t)X.nrb, 1.0);
+                buf.resize(one.size() * 8);
+                if (!one.empty()) memcpy(buf.data(), one.data(), buf.size());
+            }
+            break;
+        }
+        default: return fail(HSPMM_ERR_ARG, "unknown field");
+    }
+    *bytes = (int64_t)buf.size();
+    if (dst && capacity >= (int64_t)buf.size() && !buf.empty()) memcpy(dst, buf.data(), buf.size());
+    return HSPMM_OK;
+}
+
+void hybrid_spmm_destroy(hspmm_plan_t h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    delete h;
+}
+
+const char* hybrid_spmm_last_error(void) { return hspmm::last_error_cstr(); }
+
+const char* hybrid_spmm_version(void) { return "hspmm 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Host cost model (pure host arithmetic, no device calls).
+#include "cost_model.h"
+
+#include <cmath>
+#include <limits>
+
+namespace hspmm {
+
+RowBlockCost rowblock_cost(const MachineModel& mm, int64_t nnz, int64_t nblk, int64_t n, int sv, int sb,
+                           int br, int kc) {
+    RowBlockCost c;
+    // CSR-part: per entry a column index and a value are streamed, and one
+    // row segment of B (n elements) is gathered.
+    const double csr_stream = (double)nnz * (sv + 4);
+    const double csr_gather = (double)nnz * n * sb;
+    c.t_csr = csr_stream / mm.bw_stream + csr_gather / mm.bw_gather + nnz * mm.t_entry_csr;
+    // BCSR-part: per tile br padded values and one column index are streamed
+    // (tiles padded up to the MFMA depth kc), and one row of B is gathered
+    // per non-empty tile; the gathered row then serves all br rows.
+    const int64_t padded = nblk == 0 ? 0 : ((nblk + kc - 1) / kc) * kc;
+    const double b_stream = (double)padded * (br * sv + 4);
+    const double b_gather = (double)nblk * n * sb;
+    c.t_bcsr = b_stream / mm.bw_stream + b_gather / mm.bw_gather + nblk * mm.t_blk_bcsr;
+    return c;
+}
+
+void choose_auto(const MachineModel& mm, const std::vector<int32_t>& rb_nnz,
+                 const std::vector<int32_t>& rb_nblk, int64_t n, int sv, int sb, int br, int kc,
+                 std::vector<uint8_t>& cls, double& t_csr_total, double& t_bcsr_total) {
+    const size_t nrb = rb_nnz.size();
+    cls.assign(nrb, 0);
+    t_csr_total = 0.0;
+    t_bcsr_total = 0.0;
+    for (size_t q = 0; q < nrb; ++q) {
+        if (rb_nnz[q] == 0) continue;
+        RowBlockCost c = rowblock_cost(mm, rb_nnz[q], rb_nblk[q], n, sv, sb, br, kc);
+        if (c.t_bcsr < c.t_csr) {
+            cls[q] = 1;
+            t_bcsr_total += c.t_bcsr;
+        } else {
+            t_csr_total += c.t_csr;
+        }
+    }
+}
+
+int64_t eq1_boundary(int64_t r_total, double tp_csr, double t_csr, double tp_bcsr, double t_bcsr,
+                     int br) {
+    const double wc = tp_csr * t_csr, wb = tp_bcsr * t_bcsr;
+    if (wb <= 0.0) return r_total;
+    if (wc <= 0.0) return 0;
+    const double r = (double)r_total * wc / (wc + wb);
+    int64_t rb = (int64_t)std::floor(r / br + 0.5) * br;
+    if (rb < 0) rb = 0;
+    if (rb > r_total) rb = r_total;
+    return rb;
+}
+
+// Normal equations solved by Gaussian elimination with partial pivoting on
+// the 5 x 5 system (A^T A) a = A^T perf.
+bool fit_quadratic(const std::vector<double>& x, const std::vector<double>& y,
+                   const std::vector<double>& perf, double a[5]) {
+    const size_t n = x.size();
+    if (n < 5 || y.size() != n || perf.size() != n) return false;
+    double M[5][6] = {};
+    for (size_t s = 0; s < n; ++s) {
+        const double row[5] = {1.0, x[s], y[s], x[s] * x[s], y[s] * y[s]};
+        for (int i = 0; i < 5; ++i) {
+            for (int j = 0; j < 5; ++j) M[i][j] += row[i] * row[j];
+            M[i][5] += row[i] * perf[s];
+        }
+    }
+    for (int c = 0; c < 5; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 5; ++r)
+            if (std::fabs(M[r][c]) > std::fabs(M[p][c])) p = r;
+        if (std::fabs(M[p][c]) < 1e-300) return false;
+        if (p != c)
+            for (int j = 0; j < 6; ++j) std::swap(M[p][j], M[c][j]);
+        for (int r = 0; r < 5; ++r) {
+            if (r == c) continue;
+            const double f = M[r][c] / M[c][c];
+            for (int j = c; j < 6; ++j) M[r][j] -= f * M[c][j];
+        }
+    }
+    for (int i = 0; i < 5; ++i) a[i] = M[i][5] / M[i][i];
+    return true;
+}
+
+void argmax_quadratic(const double a[5], int T, int* bx, int* by) {
+    double best = -std::numeric_limits<double>::infinity();
+    *bx = 0;
+    *by = 0;
+    for (int x = 0; x <= T; ++x)
+        for (int y = 0; x + y <= T; ++y) {
+            if (x + y < 1) continue;
+            const double v = a[0] + a[1] * x + a[2] * y + a[3] * x * x + a[4] * y * y;
+            if (v > best) {
+                best = v;
+                *bx = x;
+                *by = y;
+            }
+        }
+}
+
+}  // namespace hspmm

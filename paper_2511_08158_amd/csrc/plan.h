@@ -1,0 +1,80 @@
+// In-memory form of a hybrid plan.
+#pragma once
+
+#include "common.h"
+#include "cost_model.h"
+
+namespace hspmm {
+
+// One sparse matrix (A, or A^T for the backward) in hybrid form.
+struct SubPlan {
+    int ct = HSPMM_F32;           // dtype of the stored part values and of the dense operand
+    int64_t m = 0, k = 0, nnz = 0;
+    int br = 16;                  // tile height B_r
+    int kc = 4;                   // tiles per MFMA step (K depth); tiles of a row block padded to it
+    int64_t nrb = 0;
+    bool scaled = false;          // FP16/BF16 values stored as value / scale[row block]
+
+    std::vector<int32_t> h_rb_nnz, h_rb_nblk;
+    std::vector<uint8_t> h_cls;   // 1 = BCSR-part
+    double pred_csr = 0.0, pred_bcsr = 0.0;
+    int64_t r_boundary = -1;
+
+    // CSR-part (Alg. 1 step 1): rows ascending, entries copied
+    int64_t rows_csr = 0, nnz_csr = 0;
+    DevBuf csr_rows, csr_ptr, csr_col, csr_val, csr_src;
+    // its work list: virtual rows of at most `seg` entries; vr_out >= 0 is a
+    // row of C, vr_out < 0 is partial slot (-vr_out - 1) of a split row
+    int64_t n_vrows = 0, n_long = 0, n_partials = 0;
+    int32_t seg = 0;
+    DevBuf vr_start, vr_end, vr_out, vr_row;
+    DevBuf long_row, long_first, long_cnt;
+
+    // BCSR-part (Alg. 1 step 2): B_r x 1 tiles, values packed in MFMA lane order
+    int64_t rb_bcsr = 0, nblk = 0, nblk_pad = 0, nnz_bcsr = 0;
+    DevBuf bcsr_rb, blk_ptr, blk_cnt, blk_col, blk_val, blk_src;
+    std::vector<int32_t> h_bcsr_rb, h_blk_ptr, h_blk_cnt;
+
+    DevBuf scale;                 // double [nrb] (scaled sub-plans only)
+
+    int64_t bytes() const;
+};
+
+struct Plan {
+    int compute = HSPMM_F32;
+    int64_t m = 0, k = 0, nnz_in = 0, nnz = 0;
+    int br = 16;
+    bool canonical = true;
+    hspmm_plan_opts opts{};
+    Allocator al;
+    MachineModel mm;
+
+    // canonicalisation (non-canonical input only)
+    DevBuf perm;          // int32 [nnz_in]: sorted position -> input entry
+    DevBuf seg;           // int32 [nnz + 1]: canonical entry -> first sorted position
+    DevBuf canon_of_orig; // int32 [nnz_in]: input entry -> canonical entry
+    DevBuf row_of;        // int32 [nnz]: row of each canonical entry
+    DevBuf canon_rp;      // int32 [m + 1]: canonical row pointer of A
+
+    SubPlan A, T;
+    bool has_T = false;
+
+    DevBuf ws;            // run/backward scratch
+    double plan_ms = 0.0;
+};
+
+// vals/row_of helpers shared by the plan build and update_values
+int pack_values(Plan& p, const void* vals, int vals_dtype, hipStream_t s);
+
+// forward product of one sub-plan: C = X * B
+int launch_forward(Plan& p, SubPlan& X, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc,
+                   hipStream_t s);
+// SDDMM on A's pattern: dA_canon[c] (or dA_in[e] via canon_of_orig)
+int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dA,
+                 hipStream_t s);
+int ensure_ws(Plan& p, size_t bytes);
+
+int build_plan(Plan& p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int vals_dtype,
+               hipStream_t s);
+
+}  // namespace hspmm

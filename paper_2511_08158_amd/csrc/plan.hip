@@ -1,0 +1,805 @@
+// Plan construction on the device: CSR validation, canonical form,
+// row-block statistics, the cost-model split, Alg. 1 (CSR-part compaction
+// and BCSR tiling with tiles in ascending column order), the transposed
+// plan, and packing of the values in the compute dtype.
+#include <algorithm>
+#include <chrono>
+
+#include "plan.h"
+#include "prim.h"
+
+namespace hspmm {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned grid_for(int64_t n, int threads = kThreads) {
+    int64_t g = ceil_div(n, threads);
+    if (g > 262144) g = 262144;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+inline unsigned grid_waves(int64_t nwaves) { return grid_for(nwaves * 64); }
+
+#define GRID_STRIDE(i, n)                                                        \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
+         i += (int64_t)gridDim.x * blockDim.x)
+#define WAVE_STRIDE(w, n)                                                                  \
+    for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < (n); \
+         w += ((int64_t)gridDim.x * blockDim.x) >> 6)
+
+enum : int32_t { FLAG_ROWPTR = 1, FLAG_COL = 2, FLAG_NONCANON = 4 };
+
+// ---------------------------------------------------------------------------
+// validation and row expansion
+// ---------------------------------------------------------------------------
+__global__ void k_check_rowptr(const int32_t* __restrict__ rp, int64_t m, int64_t nnz, int32_t* flags) {
+    GRID_STRIDE(i, m + 1) {
+        const int32_t v = rp[i];
+        bool bad = v < 0 || v > nnz;
+        if (i == 0 && v != 0) bad = true;
+        if (i == m && v != nnz) bad = true;
+        if (i < m && rp[i + 1] < v) bad = true;
+        if (bad) atomicOr(flags, FLAG_ROWPTR);
+    }
+}
+
+__global__ void k_expand_rows(const int32_t* __restrict__ rp, int64_t m, int32_t* __restrict__ row_of) {
+    const int lane = threadIdx.x & 63;
+    WAVE_STRIDE(i, m) {
+        const int32_t lo = rp[i], hi = rp[i + 1];
+        for (int32_t e = lo + lane; e < hi; e += 64) row_of[e] = (int32_t)i;
+    }
+}
+
+__global__ void k_check_cols(const int32_t* __restrict__ col, const int32_t* __restrict__ row_of, int64_t nnz,
+                             int64_t k, int32_t* flags) {
+    GRID_STRIDE(e, nnz) {
+        const int32_t c = col[e];
+        if (c < 0 || c >= k) {
+            atomicOr(flags, FLAG_COL);
+        } else if (e > 0 && row_of[e] == row_of[e - 1] && col[e - 1] >= c) {
+            atomicOr(flags, FLAG_NONCANON);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// canonical form: entries sorted by (row, col), duplicates merged
+// ---------------------------------------------------------------------------
+__global__ void k_copy_u32_from_i32(uint32_t* dst, const int32_t* src, int64_t n) {
+    GRID_STRIDE(i, n) dst[i] = (uint32_t)src[i];
+}
+
+__global__ void k_mark_heads(const int32_t* __restrict__ perm, const int32_t* __restrict__ row_of,
+                             const int32_t* __restrict__ col, int64_t n, int32_t* __restrict__ head) {
+    GRID_STRIDE(t, n) {
+        int32_t h = 1;
+        if (t > 0) {
+            const int32_t a = perm[t], b = perm[t - 1];
+            h = (row_of[a] != row_of[b] || col[a] != col[b]) ? 1 : 0;
+        }
+        head[t] = h;
+    }
+}
+
+__global__ void k_canon_build(const int32_t* __restrict__ perm, const int32_t* __restrict__ head,
+                              const int32_t* __restrict__ hx, const int32_t* __restrict__ row_of,
+                              const int32_t* __restrict__ col, int64_t n, int32_t* __restrict__ canon_of_orig,
+                              int32_t* __restrict__ seg, int32_t* __restrict__ ccol, int32_t* __restrict__ crow) {
+    GRID_STRIDE(t, n) {
+        const int32_t c = hx[t] + head[t] - 1;
+        const int32_t e = perm[t];
+        canon_of_orig[e] = c;
+        if (head[t]) {
+            seg[c] = (int32_t)t;
+            ccol[c] = col[e];
+            crow[c] = row_of[e];
+        }
+    }
+}
+
+__global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
+
+__global__ void k_count(const int32_t* __restrict__ key, int64_t n, int32_t* __restrict__ cnt) {
+    GRID_STRIDE(i, n) atomicAdd(&cnt[key[i]], 1);
+}
+
+// ---------------------------------------------------------------------------
+// row-block statistics and tiling (Alg. 1 step 2)
+// ---------------------------------------------------------------------------
+__global__ void k_gather_rb_key(uint32_t* __restrict__ key, const int32_t* __restrict__ row_of,
+                                const int32_t* __restrict__ ord, int64_t n) {
+    GRID_STRIDE(t, n) key[t] = (uint32_t)(row_of[ord[t]] >> 4);
+}
+
+__global__ void k_tile_heads(const int32_t* __restrict__ ord, const int32_t* __restrict__ row_of,
+                             const int32_t* __restrict__ col, int64_t n, int32_t* __restrict__ hd) {
+    GRID_STRIDE(t, n) {
+        int32_t h = 1;
+        if (t > 0) {
+            const int32_t a = ord[t], b = ord[t - 1];
+            h = ((row_of[a] >> 4) != (row_of[b] >> 4) || col[a] != col[b]) ? 1 : 0;
+        }
+        hd[t] = h;
+    }
+}
+
+__global__ void k_rb_nblk(const int32_t* __restrict__ rp, const int32_t* __restrict__ hx, const int32_t* total,
+                          int64_t m, int64_t nrb, int64_t n, int32_t* __restrict__ nblk) {
+    GRID_STRIDE(q, nrb) {
+        const int64_t r0 = q * 16, r1 = min(m, q * 16 + 16);
+        const int32_t s = rp[r0], e = rp[r1];
+        const int32_t hs = s < n ? hx[s] : *total;
+        const int32_t he = e < n ? hx[e] : *total;
+        nblk[q] = he - hs;
+    }
+}
+
+__host__ __device__ inline int64_t pack_index(int64_t blk, int i, bool half) {
+    // FP32/FP64: [tile][16]; FP16/BF16: per 32-tile step [tile/8 group][row][tile%8]
+    if (!half) return blk * 16 + i;
+    return (blk >> 5) * 512 + ((blk & 31) >> 3) * 128 + i * 8 + (blk & 7);
+}
+
+__global__ void k_build_csr(const int32_t* __restrict__ rows, const int32_t* __restrict__ cptr, int64_t nrows,
+                            const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const int32_t* __restrict__ src, int32_t* __restrict__ ccol,
+                            int32_t* __restrict__ csrc) {
+    const int lane = threadIdx.x & 63;
+    WAVE_STRIDE(r, nrows) {
+        const int32_t row = rows[r];
+        const int32_t lo = rp[row], len = rp[row + 1] - lo, out = cptr[r];
+        for (int32_t t = lane; t < len; t += 64) {
+            ccol[out + t] = col[lo + t];
+            csrc[out + t] = src ? src[lo + t] : lo + t;
+        }
+    }
+}
+
+__global__ void k_build_bcsr(const int32_t* __restrict__ ord, const int32_t* __restrict__ hd,
+                             const int32_t* __restrict__ hx, const int32_t* __restrict__ row_of,
+                             const int32_t* __restrict__ col, const int32_t* __restrict__ src,
+                             const int32_t* __restrict__ rp, const int32_t* __restrict__ rb_slot,
+                             const int32_t* __restrict__ blk_ptr, int64_t n, bool half,
+                             int32_t* __restrict__ blk_col, int32_t* __restrict__ blk_src) {
+    GRID_STRIDE(t, n) {
+        const int32_t x = ord[t];
+        const int32_t row = row_of[x];
+        const int32_t q = row >> 4;
+        const int32_t sl = rb_slot[q];
+        if (sl < 0) continue;
+        const int32_t gb0 = hx[rp[q * 16]];
+        const int32_t local = hx[t] + hd[t] - 1 - gb0;
+        const int64_t blk = (int64_t)blk_ptr[sl] + local;
+        if (hd[t]) blk_col[blk] = col[x];
+        blk_src[pack_index(blk, row & 15, half)] = src ? src[x] : x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// values
+// ---------------------------------------------------------------------------
+template <class T> __device__ inline double in_value(const void* v, int64_t i);
+template <> __device__ inline double in_value<double>(const void* v, int64_t i) {
+    return static_cast<const double*>(v)[i];
+}
+template <> __device__ inline double in_value<float>(const void* v, int64_t i) {
+    return (double)static_cast<const float*>(v)[i];
+}
+template <> __device__ inline double in_value<half_t>(const void* v, int64_t i) {
+    return (double)(float)static_cast<const half_t*>(v)[i];
+}
+template <> __device__ inline double in_value<bf16_t>(const void* v, int64_t i) {
+    return (double)bf16_to_float(static_cast<const bf16_t*>(v)[i]);
+}
+
+// vb[c] = sum of the input values merged into canonical entry c, in input order
+template <class T>
+__global__ void k_base_values(const void* __restrict__ vals, const int32_t* __restrict__ perm,
+                              const int32_t* __restrict__ seg, int64_t nc, double* __restrict__ vb) {
+    GRID_STRIDE(c, nc) {
+        if (!perm) {
+            vb[c] = in_value<T>(vals, c);
+        } else {
+            double s = 0.0;
+            for (int32_t t = seg[c]; t < seg[c + 1]; ++t) s += in_value<T>(vals, perm[t]);
+            vb[c] = s;
+        }
+    }
+}
+
+// scale[q] = 2^floor(log2 max |a|) over row block q (1 if all zero)
+__global__ void k_rb_scale(const int32_t* __restrict__ rp, const double* __restrict__ vb, int64_t m,
+                           int64_t nrb, double* __restrict__ scale) {
+    const int lane = threadIdx.x & 63;
+    WAVE_STRIDE(q, nrb) {
+        const int32_t lo = rp[q * 16], hi = rp[min(m, q * 16 + 16)];
+        double mx = 0.0;
+        for (int32_t e = lo + lane; e < hi; e += 64) mx = fmax(mx, fabs(vb[e]));
+        for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0) {
+            double s = 1.0;
+            if (mx > 0.0 && mx < INFINITY) {
+                int ex;
+                frexp(mx, &ex);          // mx = f 2^ex, 0.5 <= f < 1
+                s = ldexp(1.0, ex - 1);
+            }
+            scale[q] = s;
+        }
+    }
+}
+
+__device__ inline float f16_code_to_float(uint16_t c) {
+    half_t h;
+    memcpy(&h, &c, 2);
+    return (float)h;
+}
+__device__ inline float bf16_code_to_float(uint16_t c) {
+    uint32_t u = (uint32_t)c << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+// value of canonical A entry c as stored in A's parts, for the A^T parts
+__device__ inline double eff_value(int act, const double* vb, int64_t c, const double* scale,
+                                   const int32_t* row_of) {
+    const double v = vb[c];
+    switch (act) {
+        case HSPMM_F32: return (double)(float)v;
+        case HSPMM_F16: {
+            const double s = scale[row_of[c] >> 4];
+            return (double)f16_code_to_float(double_to_f16_code(v / s)) * s;
+        }
+        case HSPMM_BF16: {
+            const double s = scale[row_of[c] >> 4];
+            return (double)bf16_code_to_float(double_to_bf16_code(v / s)) * s;
+        }
+        default: return v;
+    }
+}
+
+template <class TO> __device__ inline TO to_stored(double x);
+template <> __device__ inline double to_stored<double>(double x) { return x; }
+template <> __device__ inline float to_stored<float>(double x) { return (float)x; }
+template <> __device__ inline half_t to_stored<half_t>(double x) {
+    const uint16_t c = double_to_f16_code(x);
+    half_t h;
+    memcpy(&h, &c, 2);
+    return h;
+}
+template <> __device__ inline bf16_t to_stored<bf16_t>(double x) {
+    const uint16_t c = double_to_bf16_code(x);
+    bf16_t h;
+    memcpy(&h, &c, 2);
+    return h;
+}
+
+// A's own parts: stored = value / scale[row block] in TO (scale null = 1).
+// A^T parts (act >= 0): stored = the value A's parts hold, in TO.
+template <class TO>
+__global__ void k_pack_csr(const int32_t* __restrict__ rows, const int32_t* __restrict__ cptr, int64_t nrows,
+                           const int32_t* __restrict__ csrc, const double* __restrict__ vb,
+                           const double* __restrict__ scale, int act, const double* __restrict__ a_scale,
+                           const int32_t* __restrict__ row_of, TO* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    WAVE_STRIDE(r, nrows) {
+        const int32_t row = rows[r];
+        const int32_t lo = cptr[r], hi = cptr[r + 1];
+        const double s = scale ? scale[row >> 4] : 1.0;
+        for (int32_t q = lo + lane; q < hi; q += 64) {
+            const int32_t c = csrc[q];
+            const double v = act >= 0 ? eff_value(act, vb, c, a_scale, row_of) : vb[c] / s;
+            out[q] = to_stored<TO>(v);
+        }
+    }
+}
+
+template <class TO>
+__global__ void k_pack_bcsr(const int32_t* __restrict__ rbl, const int32_t* __restrict__ bptr, int64_t nrb_b,
+                            const int32_t* __restrict__ bsrc, const double* __restrict__ vb,
+                            const double* __restrict__ scale, int act, const double* __restrict__ a_scale,
+                            const int32_t* __restrict__ row_of, TO* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    WAVE_STRIDE(sl, nrb_b) {
+        const int32_t q = rbl[sl];
+        const int64_t lo = (int64_t)bptr[sl] * 16, hi = (int64_t)bptr[sl + 1] * 16;
+        const double s = scale ? scale[q] : 1.0;
+        for (int64_t i = lo + lane; i < hi; i += 64) {
+            const int32_t c = bsrc[i];
+            double v = 0.0;
+            if (c >= 0) v = act >= 0 ? eff_value(act, vb, c, a_scale, row_of) : vb[c] / s;
+            out[i] = to_stored<TO>(v);
+        }
+    }
+}
+
+__global__ void k_transpose_fill(const int32_t* __restrict__ ord, const int32_t* __restrict__ row_of,
+                                 const int32_t* __restrict__ col, int64_t n, int32_t* __restrict__ tcol,
+                                 int32_t* __restrict__ trow) {
+    GRID_STRIDE(t, n) {
+        const int32_t c = ord[t];
+        tcol[t] = row_of[c];
+        trow[t] = col[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+template <class T>
+int upload(Allocator& al, DevBuf& b, const std::vector<T>& h, hipStream_t s) {
+    HSPMM_TRY(al.alloc(b, std::max<size_t>(1, h.size()) * sizeof(T)));
+    if (!h.empty()) HIP_TRY(hipMemcpyAsync(b.ptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return HSPMM_OK;
+}
+template <class T>
+int download(std::vector<T>& h, const void* d, size_t n, hipStream_t s) {
+    h.resize(n);
+    if (n) HIP_TRY(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return HSPMM_OK;
+}
+
+int read_flag(const int32_t* d, int32_t* h, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(h, d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return HSPMM_OK;
+}
+
+// Sort positions 0..n-1 of a canonical matrix by (row block, column), both
+// stable: returns ord, the tile-head flags hd and their exclusive scan hx.
+int tile_order(Plan& p, const int32_t* col, const int32_t* row_of, int64_t n, int64_t k, int64_t nrb,
+               DevBuf& ord, DevBuf& hd, DevBuf& hx, DevBuf& total, hipStream_t s) {
+    Allocator& al = p.al;
+    DevBuf keys, ktmp, vtmp;
+    HSPMM_TRY(al.alloc(ord, std::max<int64_t>(1, n) * 4));
+    HSPMM_TRY(al.alloc(hd, std::max<int64_t>(1, n) * 4));
+    HSPMM_TRY(al.alloc(hx, std::max<int64_t>(1, n) * 4));
+    HSPMM_TRY(al.alloc(total, 4));
+    HSPMM_TRY(al.alloc(keys, std::max<int64_t>(1, n) * 4));
+    HSPMM_TRY(al.alloc(ktmp, std::max<int64_t>(1, n) * 4));
+    HSPMM_TRY(al.alloc(vtmp, std::max<int64_t>(1, n) * 4));
+    HSPMM_TRY(iota_i32(ord.as<int32_t>(), n, s));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_copy_u32_from_i32, dim3(grid_for(n)), dim3(kThreads), 0, s, keys.as<uint32_t>(),
+                           col, n);
+        HIP_LAUNCH_CHECK();
+        HSPMM_TRY(radix_sort_pairs(keys.as<uint32_t>(), ord.as<int32_t>(), ktmp.as<uint32_t>(),
+                                   vtmp.as<int32_t>(), n, bits_for(k - 1), al, s));
+        hipLaunchKernelGGL(k_gather_rb_key, dim3(grid_for(n)), dim3(kThreads), 0, s, keys.as<uint32_t>(), row_of,
+                           ord.as<int32_t>(), n);
+        HIP_LAUNCH_CHECK();
+        HSPMM_TRY(radix_sort_pairs(keys.as<uint32_t>(), ord.as<int32_t>(), ktmp.as<uint32_t>(),
+                                   vtmp.as<int32_t>(), n, bits_for(nrb - 1), al, s));
+        hipLaunchKernelGGL(k_tile_heads, dim3(grid_for(n)), dim3(kThreads), 0, s, ord.as<int32_t>(), row_of, col,
+                           n, hd.as<int32_t>());
+        HIP_LAUNCH_CHECK();
+    }
+    HSPMM_TRY(scan_exclusive_i32(hd.as<int32_t>(), hx.as<int32_t>(), n, total.as<int32_t>(), al, s));
+    al.free(keys);
+    al.free(ktmp);
+    al.free(vtmp);
+    return HSPMM_OK;
+}
+
+// Build one sub-plan from a canonical CSR (device rp[m+1], col, row_of) whose
+// entry x stands for A's canonical entry src[x] (src null = identity).
+int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const int32_t* row_of,
+              const int32_t* src, hipStream_t s) {
+    Allocator& al = p.al;
+    const int64_t m = X.m, n = X.nnz;
+    const int br = X.br;
+    X.nrb = ceil_div(m, br);
+    const int64_t nrb = X.nrb;
+    const bool half = X.ct == HSPMM_F16 || X.ct == HSPMM_BF16;
+
+    std::vector<int32_t> h_rp;
+    HSPMM_TRY(download(h_rp, rp, (size_t)m + 1, s));
+    X.h_rb_nnz.assign(nrb, 0);
+    for (int64_t q = 0; q < nrb; ++q) X.h_rb_nnz[q] = h_rp[std::min<int64_t>(m, q * br + br)] - h_rp[q * br];
+
+    const int split = p.opts.split;
+    const bool need_tiles = split != HSPMM_SPLIT_CSR_ONLY && n > 0;
+    DevBuf ord, hd, hx, total;
+    X.h_rb_nblk.assign(nrb, 0);
+    if (need_tiles) {
+        HSPMM_TRY(tile_order(p, col, row_of, n, X.k, nrb, ord, hd, hx, total, s));
+        DevBuf dn;
+        HSPMM_TRY(al.alloc(dn, std::max<int64_t>(1, nrb) * 4));
+        hipLaunchKernelGGL(k_rb_nblk, dim3(grid_for(nrb)), dim3(kThreads), 0, s, rp, hx.as<int32_t>(),
+                           total.as<int32_t>(), m, nrb, n, dn.as<int32_t>());
+        HIP_LAUNCH_CHECK();
+        HSPMM_TRY(download(X.h_rb_nblk, dn.ptr, (size_t)nrb, s));
+        al.free(dn);
+    }
+
+    // ---- cost model: class of every row block ----
+    const int sv = (int)dtype_size(X.ct), sb = sv;
+    const int64_t nh = p.opts.n_hint > 0 ? p.opts.n_hint : 128;
+    std::vector<uint8_t> auto_cls;
+    double t_c = 0, t_b = 0;
+    choose_auto(p.mm, X.h_rb_nnz, X.h_rb_nblk, nh, sv, sb, br, X.kc, auto_cls, t_c, t_b);
+    X.h_cls.assign(nrb, 0);
+    if (split == HSPMM_SPLIT_AUTO) {
+        X.h_cls = auto_cls;
+    } else if (split == HSPMM_SPLIT_BCSR_ONLY) {
+        X.h_cls.assign(nrb, 1);
+    } else if (split == HSPMM_SPLIT_BOUNDARY) {
+        int64_t rbd = p.opts.r_boundary;
+        if (&X == &p.T || rbd < 0) {
+            // Eq. 1: the aggregate throughput of each part is m / (its
+            // predicted time for the whole matrix)
+            double all_c = 0, all_b = 0;
+            for (int64_t q = 0; q < nrb; ++q) {
+                RowBlockCost c = rowblock_cost(p.mm, X.h_rb_nnz[q], X.h_rb_nblk[q], nh, sv, sb, br, X.kc);
+                all_c += c.t_csr;
+                all_b += c.t_bcsr;
+            }
+            const double tpc = all_c > 0 ? (double)m / all_c : 1.0;
+            const double tpb = all_b > 0 ? (double)m / all_b : 1.0;
+            rbd = eq1_boundary(m, tpc, 1.0, tpb, 1.0, br);
+        }
+        if (rbd > m) rbd = m;
+        if (rbd % br != 0 && rbd != m) return fail(HSPMM_ERR_ARG, "r_boundary must be a multiple of block_rows");
+        X.r_boundary = rbd;
+        for (int64_t q = 0; q < nrb; ++q) X.h_cls[q] = (q * br >= rbd) ? 1 : 0;
+    }
+    if (!need_tiles) X.h_cls.assign(nrb, 0);
+    // predicted times of the chosen split (reported in plan_info)
+    X.pred_csr = X.pred_bcsr = 0;
+    for (int64_t q = 0; q < nrb; ++q) {
+        RowBlockCost c = rowblock_cost(p.mm, X.h_rb_nnz[q], X.h_rb_nblk[q], nh, sv, sb, br, X.kc);
+        if (X.h_cls[q]) X.pred_bcsr += c.t_bcsr; else X.pred_csr += c.t_csr;
+    }
+
+    // ---- CSR-part lists (host) ----
+    std::vector<int32_t> rows, cptr(1, 0);
+    int64_t acc = 0;
+    for (int64_t q = 0; q < nrb; ++q) {
+        if (X.h_cls[q]) continue;
+        for (int64_t r = q * br; r < std::min<int64_t>(m, q * br + br); ++r) {
+            rows.push_back((int32_t)r);
+            acc += h_rp[r + 1] - h_rp[r];
+            cptr.push_back((int32_t)acc);
+        }
+    }
+    X.rows_csr = (int64_t)rows.size();
+    X.nnz_csr = acc;
+    // virtual rows: rows longer than `seg` entries are cut into segments whose
+    // partial rows are summed in order by a second kernel
+    const int32_t seg = X.seg > 0 ? X.seg : 256;
+    X.seg = seg;
+    std::vector<int32_t> vs, ve, vo, vrow, lrow, lfirst, lcnt;
+    int64_t nparts = 0;
+    for (int64_t r = 0; r < X.rows_csr; ++r) {
+        const int32_t lo = cptr[r], hi = cptr[r + 1];
+        if (hi - lo > seg) {
+            lrow.push_back(rows[r]);
+            lfirst.push_back((int32_t)nparts);
+            int32_t c = 0;
+            for (int32_t a = lo; a < hi; a += seg) {
+                vs.push_back(a);
+                ve.push_back(std::min(hi, a + seg));
+                vo.push_back((int32_t)(-(nparts + 1)));
+                vrow.push_back(rows[r]);
+                ++nparts;
+                ++c;
+            }
+            lcnt.push_back(c);
+        }
+    }
+    for (int64_t r = 0; r < X.rows_csr; ++r) {
+        const int32_t lo = cptr[r], hi = cptr[r + 1];
+        if (hi - lo > seg) continue;
+        vs.push_back(lo);
+        ve.push_back(hi);
+        vo.push_back(rows[r]);
+        vrow.push_back(rows[r]);
+    }
+    X.n_vrows = (int64_t)vs.size();
+    X.n_long = (int64_t)lrow.size();
+    X.n_partials = nparts;
+
+    HSPMM_TRY(upload(al, X.csr_rows, rows, s));
+    HSPMM_TRY(upload(al, X.csr_ptr, cptr, s));
+    HSPMM_TRY(upload(al, X.vr_start, vs, s));
+    HSPMM_TRY(upload(al, X.vr_end, ve, s));
+    HSPMM_TRY(upload(al, X.vr_out, vo, s));
+    HSPMM_TRY(upload(al, X.vr_row, vrow, s));
+    HSPMM_TRY(upload(al, X.long_row, lrow, s));
+    HSPMM_TRY(upload(al, X.long_first, lfirst, s));
+    HSPMM_TRY(upload(al, X.long_cnt, lcnt, s));
+    HSPMM_TRY(al.alloc(X.csr_col, std::max<int64_t>(1, X.nnz_csr) * 4));
+    HSPMM_TRY(al.alloc(X.csr_src, std::max<int64_t>(1, X.nnz_csr) * 4));
+    HSPMM_TRY(al.alloc(X.csr_val, std::max<int64_t>(1, X.nnz_csr) * dtype_size(X.ct)));
+    if (X.rows_csr > 0) {
+        hipLaunchKernelGGL(k_build_csr, dim3(grid_waves(X.rows_csr)), dim3(kThreads), 0, s,
+                           X.csr_rows.as<int32_t>(), X.csr_ptr.as<int32_t>(), X.rows_csr, rp, col, src,
+                           X.csr_col.as<int32_t>(), X.csr_src.as<int32_t>());
+        HIP_LAUNCH_CHECK();
+    }
+
+    // ---- BCSR-part lists (host) ----
+    X.h_bcsr_rb.clear();
+    X.h_blk_cnt.clear();
+    X.h_blk_ptr.assign(1, 0);
+    std::vector<int32_t> rb_slot(nrb, -1);
+    int64_t pad_acc = 0;
+    X.nblk = 0;
+    X.nnz_bcsr = 0;
+    for (int64_t q = 0; q < nrb; ++q) {
+        if (!X.h_cls[q]) continue;
+        rb_slot[q] = (int32_t)X.h_bcsr_rb.size();
+        X.h_bcsr_rb.push_back((int32_t)q);
+        X.h_blk_cnt.push_back(X.h_rb_nblk[q]);
+        X.nblk += X.h_rb_nblk[q];
+        X.nnz_bcsr += X.h_rb_nnz[q];
+        pad_acc += ceil_div(X.h_rb_nblk[q], X.kc) * X.kc;
+        if (pad_acc * 16 >= (int64_t(1) << 31)) return fail(HSPMM_ERR_OVERFLOW, "padded tile slots exceed 2^31");
+        X.h_blk_ptr.push_back((int32_t)pad_acc);
+    }
+    X.rb_bcsr = (int64_t)X.h_bcsr_rb.size();
+    X.nblk_pad = pad_acc;
+    HSPMM_TRY(upload(al, X.bcsr_rb, X.h_bcsr_rb, s));
+    HSPMM_TRY(upload(al, X.blk_ptr, X.h_blk_ptr, s));
+    HSPMM_TRY(upload(al, X.blk_cnt, X.h_blk_cnt, s));
+    HSPMM_TRY(al.alloc(X.blk_col, std::max<int64_t>(1, X.nblk_pad) * 4));
+    HSPMM_TRY(al.alloc(X.blk_src, std::max<int64_t>(1, X.nblk_pad * 16) * 4));
+    HSPMM_TRY(al.alloc(X.blk_val, std::max<int64_t>(1, X.nblk_pad * 16) * dtype_size(X.ct)));
+    if (X.rb_bcsr > 0) {
+        DevBuf d_slot;
+        HSPMM_TRY(upload(al, d_slot, rb_slot, s));
+        HSPMM_TRY(fill_i32(X.blk_col.as<int32_t>(), 0, X.nblk_pad, s));
+        HSPMM_TRY(fill_i32(X.blk_src.as<int32_t>(), -1, X.nblk_pad * 16, s));
+        hipLaunchKernelGGL(k_build_bcsr, dim3(grid_for(n)), dim3(kThreads), 0, s, ord.as<int32_t>(),
+                           hd.as<int32_t>(), hx.as<int32_t>(), row_of, col, src, rp, d_slot.as<int32_t>(),
+                           X.blk_ptr.as<int32_t>(), n, half, X.blk_col.as<int32_t>(), X.blk_src.as<int32_t>());
+        HIP_LAUNCH_CHECK();
+        HIP_TRY(hipStreamSynchronize(s));
+        al.free(d_slot);
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    al.free(ord);
+    al.free(hd);
+    al.free(hx);
+    al.free(total);
+    return HSPMM_OK;
+}
+
+template <class TO>
+int pack_sub(Plan& p, SubPlan& X, const double* vb, int act, hipStream_t s) {
+    const double* scale = X.scaled ? X.scale.as<double>() : nullptr;
+    const double* a_scale = p.A.scaled ? p.A.scale.as<double>() : nullptr;
+    if (X.rows_csr > 0 && X.nnz_csr > 0) {
+        hipLaunchKernelGGL(k_pack_csr<TO>, dim3(grid_waves(X.rows_csr)), dim3(kThreads), 0, s,
+                           X.csr_rows.as<int32_t>(), X.csr_ptr.as<int32_t>(), X.rows_csr, X.csr_src.as<int32_t>(),
+                           vb, scale, act, a_scale, p.row_of.as<int32_t>(), X.csr_val.as<TO>());
+        HIP_LAUNCH_CHECK();
+    }
+    if (X.rb_bcsr > 0) {
+        hipLaunchKernelGGL(k_pack_bcsr<TO>, dim3(grid_waves(X.rb_bcsr)), dim3(kThreads), 0, s,
+                           X.bcsr_rb.as<int32_t>(), X.blk_ptr.as<int32_t>(), X.rb_bcsr, X.blk_src.as<int32_t>(),
+                           vb, scale, act, a_scale, p.row_of.as<int32_t>(), X.blk_val.as<TO>());
+        HIP_LAUNCH_CHECK();
+    }
+    return HSPMM_OK;
+}
+
+int pack_sub_any(Plan& p, SubPlan& X, const double* vb, int act, hipStream_t s) {
+    switch (X.ct) {
+        case HSPMM_F64: return pack_sub<double>(p, X, vb, act, s);
+        case HSPMM_F32: return pack_sub<float>(p, X, vb, act, s);
+        case HSPMM_F16: return pack_sub<half_t>(p, X, vb, act, s);
+        case HSPMM_BF16: return pack_sub<bf16_t>(p, X, vb, act, s);
+        default: return fail(HSPMM_ERR_DTYPE, "bad compute dtype");
+    }
+}
+
+}  // namespace
+
+int pack_values(Plan& p, const void* vals, int vals_dtype, hipStream_t s) {
+    if (p.nnz == 0) return HSPMM_OK;
+    DevBuf vb;
+    HSPMM_TRY(p.al.alloc(vb, (size_t)p.nnz * 8));
+    const int32_t* perm = p.canonical ? nullptr : p.perm.as<int32_t>();
+    const int32_t* seg = p.canonical ? nullptr : p.seg.as<int32_t>();
+    const unsigned g = grid_for(p.nnz);
+    switch (vals_dtype) {
+        case HSPMM_F64: hipLaunchKernelGGL(k_base_values<double>, dim3(g), dim3(kThreads), 0, s, vals, perm, seg, p.nnz, vb.as<double>()); break;
+        case HSPMM_F32: hipLaunchKernelGGL(k_base_values<float>, dim3(g), dim3(kThreads), 0, s, vals, perm, seg, p.nnz, vb.as<double>()); break;
+        case HSPMM_F16: hipLaunchKernelGGL(k_base_values<half_t>, dim3(g), dim3(kThreads), 0, s, vals, perm, seg, p.nnz, vb.as<double>()); break;
+        case HSPMM_BF16: hipLaunchKernelGGL(k_base_values<bf16_t>, dim3(g), dim3(kThreads), 0, s, vals, perm, seg, p.nnz, vb.as<double>()); break;
+        default: return fail(HSPMM_ERR_DTYPE, "bad vals dtype");
+    }
+    HIP_LAUNCH_CHECK();
+    if (p.A.scaled) {
+        hipLaunchKernelGGL(k_rb_scale, dim3(grid_waves(p.A.nrb)), dim3(kThreads), 0, s,
+                           p.canon_rp.as<int32_t>(), vb.as<double>(), p.m, p.A.nrb, p.A.scale.as<double>());
+        HIP_LAUNCH_CHECK();
+    }
+    HSPMM_TRY(pack_sub_any(p, p.A, vb.as<double>(), -1, s));
+    if (p.has_T) HSPMM_TRY(pack_sub_any(p, p.T, vb.as<double>(), p.compute, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    p.al.free(vb);
+    return HSPMM_OK;
+}
+
+int build_plan(Plan& p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int vals_dtype,
+               hipStream_t s) {
+    Allocator& al = p.al;
+    const int64_t m = p.m, nin = p.nnz_in;
+
+    DevBuf flags;
+    HSPMM_TRY(al.alloc(flags, 4));
+    HIP_TRY(hipMemsetAsync(flags.ptr, 0, 4, s));
+    hipLaunchKernelGGL(k_check_rowptr, dim3(grid_for(m + 1)), dim3(kThreads), 0, s, row_ptr, m, nin,
+                       flags.as<int32_t>());
+    HIP_LAUNCH_CHECK();
+    int32_t hflag = 0;
+    HSPMM_TRY(read_flag(flags.as<int32_t>(), &hflag, s));
+    if (hflag & FLAG_ROWPTR) return fail(HSPMM_ERR_CSR, "row_ptr is not a monotone 0..nnz sequence");
+
+    DevBuf row_in;  // row of every input entry
+    HSPMM_TRY(al.alloc(row_in, std::max<int64_t>(1, nin) * 4));
+    if (nin > 0) {
+        hipLaunchKernelGGL(k_expand_rows, dim3(grid_waves(m)), dim3(kThreads), 0, s, row_ptr, m,
+                           row_in.as<int32_t>());
+        HIP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_check_cols, dim3(grid_for(nin)), dim3(kThreads), 0, s, col_idx, row_in.as<int32_t>(),
+                           nin, p.k, flags.as<int32_t>());
+        HIP_LAUNCH_CHECK();
+    }
+    HSPMM_TRY(read_flag(flags.as<int32_t>(), &hflag, s));
+    if (hflag & FLAG_COL) return fail(HSPMM_ERR_CSR, "column index out of range");
+    p.canonical = !(hflag & FLAG_NONCANON);
+
+    DevBuf& crp = p.canon_rp;
+    DevBuf ccol;
+    HSPMM_TRY(al.alloc(crp, ((size_t)m + 1) * 4));
+    if (p.canonical) {
+        p.nnz = nin;
+        HSPMM_TRY(al.alloc(ccol, std::max<int64_t>(1, nin) * 4));
+        HIP_TRY(hipMemcpyAsync(crp.ptr, row_ptr, ((size_t)m + 1) * 4, hipMemcpyDeviceToDevice, s));
+        if (nin) HIP_TRY(hipMemcpyAsync(ccol.ptr, col_idx, (size_t)nin * 4, hipMemcpyDeviceToDevice, s));
+        p.row_of = std::move(row_in);
+    } else {
+        // stable sort by column, then stable sort by row: row-major order with
+        // duplicates adjacent in input order
+        DevBuf keys, ktmp, vtmp, head, hx, total;
+        HSPMM_TRY(al.alloc(p.perm, nin * 4));
+        HSPMM_TRY(al.alloc(keys, nin * 4));
+        HSPMM_TRY(al.alloc(ktmp, nin * 4));
+        HSPMM_TRY(al.alloc(vtmp, nin * 4));
+        HSPMM_TRY(iota_i32(p.perm.as<int32_t>(), nin, s));
+        hipLaunchKernelGGL(k_copy_u32_from_i32, dim3(grid_for(nin)), dim3(kThreads), 0, s, keys.as<uint32_t>(),
+                           col_idx, nin);
+        HIP_LAUNCH_CHECK();
+        HSPMM_TRY(radix_sort_pairs(keys.as<uint32_t>(), p.perm.as<int32_t>(), ktmp.as<uint32_t>(),
+                                   vtmp.as<int32_t>(), nin, bits_for(p.k - 1), al, s));
+        HSPMM_TRY(gather_key_shift(keys.as<uint32_t>(), row_in.as<int32_t>(), p.perm.as<int32_t>(), 0, nin, s));
+        HSPMM_TRY(radix_sort_pairs(keys.as<uint32_t>(), p.perm.as<int32_t>(), ktmp.as<uint32_t>(),
+                                   vtmp.as<int32_t>(), nin, bits_for(m - 1), al, s));
+        al.free(keys);
+        al.free(ktmp);
+        al.free(vtmp);
+        HSPMM_TRY(al.alloc(head, nin * 4));
+        HSPMM_TRY(al.alloc(hx, nin * 4));
+        HSPMM_TRY(al.alloc(total, 4));
+        hipLaunchKernelGGL(k_mark_heads, dim3(grid_for(nin)), dim3(kThreads), 0, s, p.perm.as<int32_t>(),
+                           row_in.as<int32_t>(), col_idx, nin, head.as<int32_t>());
+        HIP_LAUNCH_CHECK();
+        HSPMM_TRY(scan_exclusive_i32(head.as<int32_t>(), hx.as<int32_t>(), nin, total.as<int32_t>(), al, s));
+        int32_t nc = 0;
+        HSPMM_TRY(read_flag(total.as<int32_t>(), &nc, s));
+        p.nnz = nc;
+        HSPMM_TRY(al.alloc(p.seg, ((size_t)nc + 1) * 4));
+        HSPMM_TRY(al.alloc(p.canon_of_orig, nin * 4));
+        HSPMM_TRY(al.alloc(ccol, std::max<int32_t>(1, nc) * 4));
+        HSPMM_TRY(al.alloc(p.row_of, std::max<int32_t>(1, nc) * 4));
+        hipLaunchKernelGGL(k_canon_build, dim3(grid_for(nin)), dim3(kThreads), 0, s, p.perm.as<int32_t>(),
+                           head.as<int32_t>(), hx.as<int32_t>(), row_in.as<int32_t>(), col_idx, nin,
+                           p.canon_of_orig.as<int32_t>(), p.seg.as<int32_t>(), ccol.as<int32_t>(),
+                           p.row_of.as<int32_t>());
+        HIP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, p.seg.as<int32_t>() + nc, (int32_t)nin);
+        HIP_LAUNCH_CHECK();
+        // canonical row pointer from per-row counts
+        DevBuf cnt;
+        HSPMM_TRY(al.alloc(cnt, ((size_t)m + 1) * 4));
+        HIP_TRY(hipMemsetAsync(cnt.ptr, 0, ((size_t)m + 1) * 4, s));
+        hipLaunchKernelGGL(k_count, dim3(grid_for(nc)), dim3(kThreads), 0, s, p.row_of.as<int32_t>(), (int64_t)nc,
+                           cnt.as<int32_t>());
+        HIP_LAUNCH_CHECK();
+        HSPMM_TRY(scan_exclusive_i32(cnt.as<int32_t>(), crp.as<int32_t>(), m + 1, nullptr, al, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        al.free(cnt);
+        al.free(head);
+        al.free(hx);
+        al.free(total);
+        al.free(row_in);
+    }
+
+    // ---- A's sub-plan ----
+    SubPlan& A = p.A;
+    A.ct = p.compute;
+    A.m = m;
+    A.k = p.k;
+    A.nnz = p.nnz;
+    A.br = p.br;
+    A.kc = (p.compute == HSPMM_F16 || p.compute == HSPMM_BF16) ? 32 : 4;
+    A.scaled = (p.compute == HSPMM_F16 || p.compute == HSPMM_BF16);
+    HSPMM_TRY(build_sub(p, A, crp.as<int32_t>(), ccol.as<int32_t>(), p.row_of.as<int32_t>(), nullptr, s));
+    if (A.scaled) HSPMM_TRY(al.alloc(A.scale, std::max<int64_t>(1, A.nrb) * 8));
+
+    // ---- transposed sub-plan for dB = A^T dC ----
+    if (p.opts.want_backward) {
+        SubPlan& T = p.T;
+        T.ct = p.compute == HSPMM_F64 ? HSPMM_F64 : HSPMM_F32;
+        T.m = p.k;
+        T.k = m;
+        T.nnz = p.nnz;
+        T.br = p.br;
+        T.kc = 4;
+        T.scaled = false;
+        DevBuf ord, keys, ktmp, vtmp, tcol, trow, trp, cnt;
+        const int64_t nc = p.nnz;
+        HSPMM_TRY(al.alloc(ord, std::max<int64_t>(1, nc) * 4));
+        HSPMM_TRY(al.alloc(keys, std::max<int64_t>(1, nc) * 4));
+        HSPMM_TRY(al.alloc(ktmp, std::max<int64_t>(1, nc) * 4));
+        HSPMM_TRY(al.alloc(vtmp, std::max<int64_t>(1, nc) * 4));
+        HSPMM_TRY(iota_i32(ord.as<int32_t>(), nc, s));
+        if (nc > 0) {
+            hipLaunchKernelGGL(k_copy_u32_from_i32, dim3(grid_for(nc)), dim3(kThreads), 0, s, keys.as<uint32_t>(),
+                               ccol.as<int32_t>(), nc);
+            HIP_LAUNCH_CHECK();
+            HSPMM_TRY(radix_sort_pairs(keys.as<uint32_t>(), ord.as<int32_t>(), ktmp.as<uint32_t>(),
+                                       vtmp.as<int32_t>(), nc, bits_for(p.k - 1), al, s));
+        }
+        al.free(keys);
+        al.free(ktmp);
+        al.free(vtmp);
+        HSPMM_TRY(al.alloc(tcol, std::max<int64_t>(1, nc) * 4));
+        HSPMM_TRY(al.alloc(trow, std::max<int64_t>(1, nc) * 4));
+        HSPMM_TRY(al.alloc(trp, ((size_t)p.k + 1) * 4));
+        HSPMM_TRY(al.alloc(cnt, ((size_t)p.k + 1) * 4));
+        HIP_TRY(hipMemsetAsync(cnt.ptr, 0, ((size_t)p.k + 1) * 4, s));
+        if (nc > 0) {
+            hipLaunchKernelGGL(k_transpose_fill, dim3(grid_for(nc)), dim3(kThreads), 0, s, ord.as<int32_t>(),
+                               p.row_of.as<int32_t>(), ccol.as<int32_t>(), nc, tcol.as<int32_t>(),
+                               trow.as<int32_t>());
+            HIP_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_count, dim3(grid_for(nc)), dim3(kThreads), 0, s, trow.as<int32_t>(), nc,
+                               cnt.as<int32_t>());
+            HIP_LAUNCH_CHECK();
+        }
+        HSPMM_TRY(scan_exclusive_i32(cnt.as<int32_t>(), trp.as<int32_t>(), p.k + 1, nullptr, al, s));
+        HSPMM_TRY(build_sub(p, T, trp.as<int32_t>(), tcol.as<int32_t>(), trow.as<int32_t>(), ord.as<int32_t>(), s));
+        HIP_TRY(hipStreamSynchronize(s));
+        p.has_T = true;
+    }
+    al.free(ccol);
+
+    HSPMM_TRY(pack_values(p, vals, vals_dtype, s));
+
+    // scratch for split rows (sized for n up to max(n_hint, 256)) and, for
+    // non-canonical inputs, the canonical dA buffer
+    const int64_t nmax = std::max<int64_t>(256, p.opts.n_hint);
+    const size_t acc_b = p.compute == HSPMM_F64 ? 8 : 4;
+    size_t need = (size_t)std::max(p.A.n_partials, p.has_T ? p.T.n_partials : 0) * nmax * acc_b;
+    if (!p.canonical) need = std::max(need, (size_t)p.nnz * acc_b);
+    HSPMM_TRY(ensure_ws(p, need));
+    HIP_TRY(hipStreamSynchronize(s));
+    return HSPMM_OK;
+}
+
+int64_t SubPlan::bytes() const {
+    return (int64_t)(csr_rows.bytes + csr_ptr.bytes + csr_col.bytes + csr_val.bytes + csr_src.bytes +
+                     vr_start.bytes + vr_end.bytes + vr_out.bytes + vr_row.bytes + long_row.bytes + long_first.bytes +
+                     long_cnt.bytes + bcsr_rb.bytes + blk_ptr.bytes + blk_cnt.bytes + blk_col.bytes +
+                     blk_val.bytes + blk_src.bytes + scale.bytes);
+}
+
+}  // namespace hspmm

@@ -1,0 +1,349 @@
+// dA = SDDMM(dC, B) on A's pattern: dA[e] = <dC[row(e),:], B[col(e),:]>.
+//
+// CSR-part: the work list of the forward CSR kernel; a lane group holds its
+// row of dC in registers, fetches one B row segment per entry and reduces
+// the dot product across the group.
+// BCSR-part: per row block, the 16 x n slab of dC times the gathered B rows
+// of 16 tiles at a time is one 16 x 16 MFMA product (K = the n columns);
+// only the slots that hold an entry of A are written.
+#include "plan.h"
+
+namespace hspmm {
+
+namespace {
+
+struct SddArgs {
+    // CSR-part
+    const int32_t* vr_start;
+    const int32_t* vr_end;
+    const int32_t* vr_row;
+    const int32_t* col;
+    const int32_t* dst;    // canonical entry of each CSR-part entry
+    int64_t n_vrows;
+    // BCSR-part
+    const int32_t* rb;
+    const int32_t* blk_ptr;
+    const int32_t* blk_cnt;
+    const int32_t* blk_col;
+    const int32_t* blk_src;
+    int64_t n_rb;
+    bool half_pack;
+    // dense operands
+    const void* B;
+    int64_t ldb;
+    const void* dC;
+    int64_t lddc;
+    int64_t n;
+    int64_t m;
+    void* dA;
+};
+
+__host__ __device__ inline int64_t pack_index(int64_t blk, int i, bool half) {
+    if (!half) return blk * 16 + i;
+    return (blk >> 5) * 512 + ((blk & 31) >> 3) * 128 + i * 8 + (blk & 7);
+}
+
+template <class T, int N>
+__device__ inline void load_as(const T* p, typename Elem<T>::acc_t (&out)[N]) {
+    if constexpr (N == 1) {
+        out[0] = Elem<T>::to_acc(*p);
+    } else {
+        typedef T V __attribute__((ext_vector_type(N)));
+        const V v = *reinterpret_cast<const V*>(p);
+#pragma unroll
+        for (int i = 0; i < N; ++i) out[i] = Elem<T>::to_acc(v[i]);
+    }
+}
+
+// TB = storage type of B; TG = dC / dA type (= accumulation type)
+template <class TB, class TG, int VEC, int LPR>
+__device__ void sdd_csr_wave(const SddArgs& a, int64_t wave) {
+    constexpr int R = 64 / LPR;
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63;
+    const int g = lane / LPR, gl = lane % LPR;
+    if (wave * R >= a.n_vrows) return;
+    const int64_t vr = wave * R + g;
+    const bool act = vr < a.n_vrows;
+    const int start = act ? a.vr_start[vr] : 0;
+    const int len = act ? a.vr_end[vr] - start : 0;
+    const int row = act ? a.vr_row[vr] : 0;
+    int maxlen = len;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o, 64));
+    const TB* __restrict__ B = static_cast<const TB*>(a.B);
+    const TG* __restrict__ dC = static_cast<const TG*>(a.dC);
+    TG* __restrict__ dA = static_cast<TG*>(a.dA);
+    const bool one_panel = a.n <= (int64_t)LPR * VEC;
+    const int64_t col0 = (int64_t)gl * VEC;
+    TG g0[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) g0[v] = TG(0);
+    if (one_panel && act && col0 < a.n) load_as<TG, VEC>(dC + (int64_t)row * a.lddc + col0, g0);
+
+    for (int base = 0; base < maxlen; base += LPR) {
+        const bool eok = base + gl < len;
+        const int e = start + base + gl;
+        const int my_col = eok ? a.col[e] : -1;
+        const int my_dst = eok ? a.dst[e] : -1;
+        const int cnt = min(LPR, maxlen - base);
+        for (int u0 = 0; u0 < cnt; u0 += U) {
+            int cc[U], dd[U];
+            TG part[U];
+#pragma unroll
+            for (int uu = 0; uu < U; ++uu) {
+                cc[uu] = __shfl(my_col, (u0 + uu) & (LPR - 1), LPR);
+                dd[uu] = __shfl(my_dst, (u0 + uu) & (LPR - 1), LPR);
+                if (u0 + uu >= cnt) cc[uu] = -1;
+                part[uu] = TG(0);
+            }
+            if (one_panel) {
+#pragma unroll
+                for (int uu = 0; uu < U; ++uu) {
+                    if (cc[uu] >= 0 && col0 < a.n) {
+                        TG bv[VEC];
+                        load_as<TB, VEC>(B + (int64_t)cc[uu] * a.ldb + col0, bv);
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v) part[uu] += g0[v] * bv[v];
+                    }
+                }
+            } else {
+                for (int64_t c0 = col0; c0 < a.n; c0 += (int64_t)LPR * VEC) {
+                    TG gv[VEC];
+                    load_as<TG, VEC>(dC + (int64_t)row * a.lddc + c0, gv);
+#pragma unroll
+                    for (int uu = 0; uu < U; ++uu) {
+                        if (cc[uu] >= 0) {
+                            TG bv[VEC];
+                            load_as<TB, VEC>(B + (int64_t)cc[uu] * a.ldb + c0, bv);
+#pragma unroll
+                            for (int v = 0; v < VEC; ++v) part[uu] += gv[v] * bv[v];
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = LPR / 2; o >= 1; o >>= 1)
+#pragma unroll
+                for (int uu = 0; uu < U; ++uu) part[uu] += __shfl_xor(part[uu], o, LPR);
+            if (gl == 0) {
+#pragma unroll
+                for (int uu = 0; uu < U; ++uu)
+                    if (cc[uu] >= 0) dA[dd[uu]] = part[uu];
+            }
+        }
+    }
+}
+
+__device__ inline f4_t mfma4(float a, float b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline d4_t mfma4(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <class T> struct AccOf;
+template <> struct AccOf<float> { typedef f4_t type; };
+template <> struct AccOf<double> { typedef d4_t type; };
+template <class T> __device__ inline int out_row(int g, int r) { return 4 * g + r; }
+template <> __device__ inline int out_row<double>(int g, int r) { return g + 4 * r; }
+
+// One wave per row block.  K of the MFMA runs over the n columns: lane
+// (i, q) supplies columns kbase + q*VEC + v of dC row i and of B row j, so
+// each of the VEC MFMAs of a step consumes one component.  When n fits in
+// NKR steps, the dC slab stays in registers across all tile chunks.
+template <class TB, class TG, int VEC, int NKR>
+__device__ void sdd_bcsr_wave(const SddArgs& a, int64_t slot) {
+    typedef typename AccOf<TG>::type acc_v;
+    if (slot >= a.n_rb) return;
+    const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
+    const int rb = a.rb[slot];
+    const int b0 = a.blk_ptr[slot];
+    const int cnt = a.blk_cnt[slot];
+    const TB* __restrict__ B = static_cast<const TB*>(a.B);
+    const TG* __restrict__ dC = static_cast<const TG*>(a.dC);
+    TG* __restrict__ dA = static_cast<TG*>(a.dA);
+    constexpr int STEP = 4 * VEC;
+    const int64_t arow = (int64_t)rb * 16 + j;
+    const bool arow_ok = arow < a.m;
+    const int nsteps = (int)ceil_div(a.n, STEP);
+    const bool cached = nsteps <= NKR;
+    TG gc[NKR][VEC];
+    if (cached) {
+#pragma unroll
+        for (int s = 0; s < NKR; ++s) {
+            const int64_t c = (int64_t)s * STEP + q * VEC;
+            if (s < nsteps && arow_ok && c < a.n) {
+                load_as<TG, VEC>(dC + arow * a.lddc + c, gc[s]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) gc[s][v] = TG(0);
+            }
+        }
+    }
+    for (int c0 = 0; c0 < cnt; c0 += 16) {
+        const bool bok = c0 + j < cnt;
+        const int bc = bok ? a.blk_col[b0 + c0 + j] : 0;
+        acc_v acc = acc_v{0, 0, 0, 0};
+        if (cached) {
+#pragma unroll
+            for (int s = 0; s < NKR; ++s) {
+                if (s >= nsteps) break;
+                const int64_t c = (int64_t)s * STEP + q * VEC;
+                TG bv[VEC];
+                if (bok && c < a.n) {
+                    load_as<TB, VEC>(B + (int64_t)bc * a.ldb + c, bv);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) bv[v] = TG(0);
+                }
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc = mfma4(gc[s][v], bv[v], acc);
+            }
+        } else {
+            for (int s = 0; s < nsteps; ++s) {
+                const int64_t c = (int64_t)s * STEP + q * VEC;
+                TG gv[VEC], bv[VEC];
+                if (arow_ok && c < a.n) {
+                    load_as<TG, VEC>(dC + arow * a.lddc + c, gv);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) gv[v] = TG(0);
+                }
+                if (bok && c < a.n) {
+                    load_as<TB, VEC>(B + (int64_t)bc * a.ldb + c, bv);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) bv[v] = TG(0);
+                }
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc = mfma4(gv[v], bv[v], acc);
+            }
+        }
+        // lane (j, q) holds rows out_row(q, r) of tile c0 + j
+        if (bok) {
+            const int64_t blk = (int64_t)b0 + c0 + j;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = out_row<TG>(q, r);
+                const int32_t d = a.blk_src[pack_index(blk, i, a.half_pack)];
+                if (d >= 0) dA[d] = acc[r];
+            }
+        }
+    }
+}
+
+template <class TB, class TG, int VEC, int LPR, int BVEC, int NKR>
+__global__ __launch_bounds__(256) void k_sddmm(SddArgs a, uint32_t g_bcsr, uint32_t g_csr) {
+    const uint32_t bid = blockIdx.x;
+    const int w = threadIdx.x >> 6;
+    if (bid < g_bcsr) {
+        sdd_bcsr_wave<TB, TG, BVEC, NKR>(a, (int64_t)xcd_remap(bid, g_bcsr) * 4 + w);
+    } else {
+        sdd_csr_wave<TB, TG, VEC, LPR>(a, (int64_t)xcd_remap(bid - g_bcsr, g_csr) * 4 + w);
+    }
+}
+
+template <class TG>
+__global__ void k_gather_dA(const TG* __restrict__ canon, const int32_t* __restrict__ idx, int64_t n,
+                            TG* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = canon[idx[i]];
+}
+
+inline uint32_t pad8(int64_t g) { return (uint32_t)(ceil_div(g, 8) * 8); }
+
+inline int lpr_for(int64_t n, int vec) {
+    int64_t need = ceil_div(n, vec);
+    int l = 4;
+    while (l < 64 && l < need) l <<= 1;
+    return l;
+}
+
+template <class TB, class TG, int VEC, int LPR, int BVEC, int NKR>
+int launch_sdd(const SubPlan& X, SddArgs a, hipStream_t s) {
+    constexpr int R = 64 / LPR;
+    const int64_t csr_waves = ceil_div(X.n_vrows, R);
+    const uint32_t g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
+    const uint32_t g_bcsr = X.rb_bcsr ? pad8(ceil_div(X.rb_bcsr, 4)) : 0;
+    if (g_csr + g_bcsr == 0) return HSPMM_OK;
+    hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR>), dim3(g_bcsr + g_csr), dim3(256), 0, s, a, g_bcsr,
+                       g_csr);
+    HIP_LAUNCH_CHECK();
+    return HSPMM_OK;
+}
+
+#define HSPMM_LPR_SWITCH(LPRV, ...)                               \
+    switch (LPRV) {                                               \
+        case 4: { constexpr int LPR = 4; __VA_ARGS__; } break;   \
+        case 8: { constexpr int LPR = 8; __VA_ARGS__; } break;   \
+        case 16: { constexpr int LPR = 16; __VA_ARGS__; } break; \
+        case 32: { constexpr int LPR = 32; __VA_ARGS__; } break; \
+        default: { constexpr int LPR = 64; __VA_ARGS__; } break; \
+    }
+
+inline bool aligned(const void* p, size_t al) { return ((uintptr_t)p % al) == 0; }
+
+}  // namespace
+
+int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dA,
+                 hipStream_t s) {
+    SubPlan& X = p.A;
+    if (p.nnz == 0) return HSPMM_OK;
+    const size_t go = p.compute == HSPMM_F64 ? 8 : 4;
+    void* target = dA;
+    if (!p.canonical) {
+        HSPMM_TRY(ensure_ws(p, (size_t)p.nnz * go));
+        target = p.ws.ptr;
+    }
+    if (n == 0) {
+        HIP_TRY(hipMemsetAsync(target, 0, (size_t)p.nnz * go, s));
+    } else {
+        SddArgs a{X.vr_start.as<int32_t>(), X.vr_end.as<int32_t>(), X.vr_row.as<int32_t>(), X.csr_col.as<int32_t>(),
+                  X.csr_src.as<int32_t>(), X.n_vrows, X.bcsr_rb.as<int32_t>(), X.blk_ptr.as<int32_t>(),
+                  X.blk_cnt.as<int32_t>(), X.blk_col.as<int32_t>(), X.blk_src.as<int32_t>(), X.rb_bcsr,
+                  X.ct == HSPMM_F16 || X.ct == HSPMM_BF16, B, ldb, dC, lddc, n, X.m, target};
+        const size_t eb = dtype_size(X.ct);
+        const int rc = [&]() -> int {
+            switch (X.ct) {
+                case HSPMM_F32: {
+                    const bool v = n % 4 == 0 && ldb % 4 == 0 && lddc % 4 == 0 && aligned(B, 16) && aligned(dC, 16);
+                    if (!v) return launch_sdd<float, float, 1, 64, 1, 32>(X, a, s);
+                    HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<float, float, 4, LPR, 4, 8>(X, a, s)));
+                }
+                case HSPMM_F64: {
+                    const bool v = n % 2 == 0 && ldb % 2 == 0 && lddc % 2 == 0 && aligned(B, 16) && aligned(dC, 16);
+                    if (!v) return launch_sdd<double, double, 1, 64, 1, 32>(X, a, s);
+                    HSPMM_LPR_SWITCH(lpr_for(n, 2), return (launch_sdd<double, double, 2, LPR, 2, 16>(X, a, s)));
+                }
+                case HSPMM_F16: {
+                    const bool v = n % 4 == 0 && ldb % 4 == 0 && lddc % 4 == 0 && aligned(B, 8) && aligned(dC, 16);
+                    if (!v) return launch_sdd<half_t, float, 1, 64, 1, 32>(X, a, s);
+                    HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<half_t, float, 4, LPR, 4, 8>(X, a, s)));
+                }
+                case HSPMM_BF16: {
+                    const bool v = n % 4 == 0 && ldb % 4 == 0 && lddc % 4 == 0 && aligned(B, 8) && aligned(dC, 16);
+                    if (!v) return launch_sdd<bf16_t, float, 1, 64, 1, 32>(X, a, s);
+                    HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<bf16_t, float, 4, LPR, 4, 8>(X, a, s)));
+                }
+                default: return fail(HSPMM_ERR_DTYPE, "bad compute dtype");
+            }
+            return HSPMM_OK;
+        }();
+        (void)eb;
+        HSPMM_TRY(rc);
+    }
+    if (!p.canonical) {
+        const unsigned g = (unsigned)std::min<int64_t>(ceil_div(p.nnz_in, 256), 65536);
+        if (go == 8) {
+            hipLaunchKernelGGL(k_gather_dA<double>, dim3(g), dim3(256), 0, s, p.ws.as<double>(),
+                               p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<double*>(dA));
+        } else {
+            hipLaunchKernelGGL(k_gather_dA<float>, dim3(g), dim3(256), 0, s, p.ws.as<float>(),
+                               p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<float*>(dA));
+        }
+        HIP_LAUNCH_CHECK();
+    }
+    return HSPMM_OK;
+}
+
+}  // namespace hspmm

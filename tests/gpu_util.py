@@ -1,0 +1,49 @@
+"""Helpers shared by the GPU tests: build plans through the C ABI binding and
+compare against the FP64 oracle."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+from oracle import loops_ref as L
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5, torch.float16: 5e-3, torch.bfloat16: 5e-3}
+SPLITS = ("auto", "csr", "bcsr", "boundary")
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def to_dev(x, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(dev())
+
+
+def quantized_dense(B, dtype):
+    """B rounded to `dtype` (torch's conversion), returned as FP64 numpy."""
+    return torch.as_tensor(B).to(dtype).to(torch.float64).numpy()
+
+
+def effective_vals(a_m, row_ptr, vals, dtype):
+    """Values of A as the plan stores them, in FP64: FP64 exact, FP32
+    rounded, FP16/BF16 quantised per 16-row block (oracle's quantize_ref)."""
+    if dtype == torch.float64:
+        return np.asarray(vals, dtype=np.float64)
+    if dtype == torch.float32:
+        return np.asarray(vals, dtype=np.float64).astype(np.float32).astype(np.float64)
+    fmt = "f16" if dtype == torch.float16 else "bf16"
+    _, _, deq = L.quantize_ref(a_m, row_ptr, vals, 16, fmt)
+    return deq
+
+
+def oracle_forward(a, B):
+    return oracle.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, B)
+
+
+def make_plan(hs, a, dtype, split="auto", backward=False, vals_dtype=torch.float64, **kw):
+    return hs.Plan(a.row_ptr, a.col_idx, to_dev(a.vals, vals_dtype), (a.m, a.k), compute=dtype,
+                   split=split, backward=backward, **kw)
