@@ -187,9 +187,11 @@ class Plan:
 class _HybridSpMM(torch.autograd.Function):
     @staticmethod
     def forward(ctx, vals, B, plan):
+        # learnable values change every step: re-pack them; a static A is
+        # packed once at plan time
         key = (vals.data_ptr(), vals._version)
-        if key != plan._vals_key:
-            plan.update_values(vals)
+        if vals.requires_grad or key != plan._vals_key:
+            plan.update_values(vals.detach())
         C = plan.run(B)
         ctx.plan = plan
         ctx.save_for_backward(B)

@@ -55,11 +55,17 @@ __device__ inline void load_as(const T* p, typename Elem<T>::acc_t (&out)[N]) {
     }
 }
 
-// TB = storage type of B; TG = dC / dA type (= accumulation type)
+// TB = storage type of B; TG = dC / dA type (= accumulation type).
+// U entries are reduced across the LPR lanes of a group together: each
+// butterfly stage halves the number of partial sums a lane holds (one
+// shuffle per pair), so U dot products cost U - 1 + log2(LPR / U) shuffles
+// instead of U log2(LPR); afterwards lane gl holds the sum of entry
+// (gl / (LPR / U)) of the batch.
 template <class TB, class TG, int VEC, int LPR>
 __device__ void sdd_csr_wave(const SddArgs& a, int64_t wave) {
     constexpr int R = 64 / LPR;
-    constexpr int U = 4;
+    constexpr int U = LPR < 16 ? LPR : 16;
+    constexpr int SPAN = LPR / U;  // lanes that end with the same entry
     const int lane = threadIdx.x & 63;
     const int g = lane / LPR, gl = lane % LPR;
     if (wave * R >= a.n_vrows) return;
@@ -88,21 +94,16 @@ __device__ void sdd_csr_wave(const SddArgs& a, int64_t wave) {
         const int my_dst = eok ? a.dst[e] : -1;
         const int cnt = min(LPR, maxlen - base);
         for (int u0 = 0; u0 < cnt; u0 += U) {
-            int cc[U], dd[U];
             TG part[U];
 #pragma unroll
-            for (int uu = 0; uu < U; ++uu) {
-                cc[uu] = __shfl(my_col, (u0 + uu) & (LPR - 1), LPR);
-                dd[uu] = __shfl(my_dst, (u0 + uu) & (LPR - 1), LPR);
-                if (u0 + uu >= cnt) cc[uu] = -1;
-                part[uu] = TG(0);
-            }
+            for (int uu = 0; uu < U; ++uu) part[uu] = TG(0);
             if (one_panel) {
 #pragma unroll
                 for (int uu = 0; uu < U; ++uu) {
-                    if (cc[uu] >= 0 && col0 < a.n) {
+                    const int c = __shfl(my_col, (u0 + uu) & (LPR - 1), LPR);
+                    if (c >= 0 && u0 + uu < cnt && col0 < a.n) {
                         TG bv[VEC];
-                        load_as<TB, VEC>(B + (int64_t)cc[uu] * a.ldb + col0, bv);
+                        load_as<TB, VEC>(B + (int64_t)c * a.ldb + col0, bv);
 #pragma unroll
                         for (int v = 0; v < VEC; ++v) part[uu] += g0[v] * bv[v];
                     }
@@ -113,24 +114,33 @@ __device__ void sdd_csr_wave(const SddArgs& a, int64_t wave) {
                     load_as<TG, VEC>(dC + (int64_t)row * a.lddc + c0, gv);
 #pragma unroll
                     for (int uu = 0; uu < U; ++uu) {
-                        if (cc[uu] >= 0) {
+                        const int c = __shfl(my_col, (u0 + uu) & (LPR - 1), LPR);
+                        if (c >= 0 && u0 + uu < cnt) {
                             TG bv[VEC];
-                            load_as<TB, VEC>(B + (int64_t)cc[uu] * a.ldb + c0, bv);
+                            load_as<TB, VEC>(B + (int64_t)c * a.ldb + c0, bv);
 #pragma unroll
                             for (int v = 0; v < VEC; ++v) part[uu] += gv[v] * bv[v];
                         }
                     }
                 }
             }
+            // halving butterfly over the offsets LPR/2 .. SPAN
 #pragma unroll
-            for (int o = LPR / 2; o >= 1; o >>= 1)
+            for (int nv = U, o = LPR / 2; nv > 1; nv >>= 1, o >>= 1) {
+                const bool up = (gl & o) != 0;
 #pragma unroll
-                for (int uu = 0; uu < U; ++uu) part[uu] += __shfl_xor(part[uu], o, LPR);
-            if (gl == 0) {
-#pragma unroll
-                for (int uu = 0; uu < U; ++uu)
-                    if (cc[uu] >= 0) dA[dd[uu]] = part[uu];
+                for (int i = 0; i < nv / 2; ++i) {
+                    const TG keep = up ? part[i + nv / 2] : part[i];
+                    const TG send = up ? part[i] : part[i + nv / 2];
+                    part[i] = keep + __shfl_xor(send, o, LPR);
+                }
             }
+#pragma unroll
+            for (int o = SPAN / 2; o >= 1; o >>= 1) part[0] += __shfl_xor(part[0], o, LPR);
+            const int idx = u0 + gl / SPAN;
+            const int d = __shfl(my_dst, idx & (LPR - 1), LPR);
+            const int c = __shfl(my_col, idx & (LPR - 1), LPR);
+            if ((gl % SPAN) == 0 && idx < cnt && c >= 0) dA[d] = part[0];
         }
     }
 }
@@ -147,15 +157,17 @@ template <> struct AccOf<double> { typedef d4_t type; };
 template <class T> __device__ inline int out_row(int g, int r) { return 4 * g + r; }
 template <> __device__ inline int out_row<double>(int g, int r) { return g + 4 * r; }
 
-// One wave per row block.  K of the MFMA runs over the n columns: lane
-// (i, q) supplies columns kbase + q*VEC + v of dC row i and of B row j, so
-// each of the VEC MFMAs of a step consumes one component.  When n fits in
-// NKR steps, the dC slab stays in registers across all tile chunks.
+// One workgroup per row block.  K of the MFMA runs over the n columns:
+// lane (i, q) supplies columns kbase + q*VEC + v of dC row i and of B row j,
+// so each of the VEC MFMAs of a step consumes one component.  When n fits in
+// NKR steps the 16 x n slab of dC is staged once in LDS and held in
+// registers by all four waves; the row block's chunks of 16 tiles are dealt
+// to the waves round-robin (independent outputs, no reduction needed).
 template <class TB, class TG, int VEC, int NKR>
-__device__ void sdd_bcsr_wave(const SddArgs& a, int64_t slot) {
+__device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
     typedef typename AccOf<TG>::type acc_v;
-    if (slot >= a.n_rb) return;
-    const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
+    if (slot >= a.n_rb) return;  // uniform over the workgroup
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane & 15, q = lane >> 4;
     const int rb = a.rb[slot];
     const int b0 = a.blk_ptr[slot];
     const int cnt = a.blk_cnt[slot];
@@ -163,70 +175,79 @@ __device__ void sdd_bcsr_wave(const SddArgs& a, int64_t slot) {
     const TG* __restrict__ dC = static_cast<const TG*>(a.dC);
     TG* __restrict__ dA = static_cast<TG*>(a.dA);
     constexpr int STEP = 4 * VEC;
+    constexpr int NMAX = NKR * STEP;
+    constexpr int LDR = NMAX + 4;  // padded LDS row
     const int64_t arow = (int64_t)rb * 16 + j;
     const bool arow_ok = arow < a.m;
     const int nsteps = (int)ceil_div(a.n, STEP);
     const bool cached = nsteps <= NKR;
     TG gc[NKR][VEC];
     if (cached) {
-#pragma unroll
-        for (int s = 0; s < NKR; ++s) {
-            const int64_t c = (int64_t)s * STEP + q * VEC;
-            if (s < nsteps && arow_ok && c < a.n) {
-                load_as<TG, VEC>(dC + arow * a.lddc + c, gc[s]);
-            } else {
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) gc[s][v] = TG(0);
-            }
+        for (int idx = threadIdx.x; idx < 16 * NMAX; idx += 256) {
+            const int i = idx / NMAX, c = idx - i * NMAX;
+            const int64_t row = (int64_t)rb * 16 + i;
+            lds[i * LDR + c] = (row < a.m && c < a.n) ? dC[row * a.lddc + c] : TG(0);
         }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NKR; ++s)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) gc[s][v] = lds[j * LDR + s * STEP + q * VEC + v];
     }
-    for (int c0 = 0; c0 < cnt; c0 += 16) {
-        const bool bok = c0 + j < cnt;
-        const int bc = bok ? a.blk_col[b0 + c0 + j] : 0;
-        acc_v acc = acc_v{0, 0, 0, 0};
-        if (cached) {
+    for (int it0 = 0; 16 * w + 64 * it0 < cnt; it0 += 4) {
+        // tile columns of this wave's next four chunks: lane l -> chunk it0 + l/16
+        const int pre = 16 * w + 64 * (it0 + (lane >> 4)) + j;
+        const int colreg = pre < cnt ? a.blk_col[b0 + pre] : 0;
+        for (int it = it0; it < it0 + 4; ++it) {
+            const int c0 = 16 * w + 64 * it;
+            if (c0 >= cnt) break;
+            const bool bok = c0 + j < cnt;
+            const int bc = __shfl(colreg, (16 * (it - it0) + j) & 63, 64);
+            acc_v acc = acc_v{0, 0, 0, 0};
+            if (cached) {
 #pragma unroll
-            for (int s = 0; s < NKR; ++s) {
-                if (s >= nsteps) break;
-                const int64_t c = (int64_t)s * STEP + q * VEC;
-                TG bv[VEC];
-                if (bok && c < a.n) {
-                    load_as<TB, VEC>(B + (int64_t)bc * a.ldb + c, bv);
-                } else {
+                for (int s = 0; s < NKR; ++s) {
+                    if (s >= nsteps) break;
+                    const int64_t c = (int64_t)s * STEP + q * VEC;
+                    TG bv[VEC];
+                    if (bok && c < a.n) {
+                        load_as<TB, VEC>(B + (int64_t)bc * a.ldb + c, bv);
+                    } else {
 #pragma unroll
-                    for (int v = 0; v < VEC; ++v) bv[v] = TG(0);
+                        for (int v = 0; v < VEC; ++v) bv[v] = TG(0);
+                    }
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) acc = mfma4(gc[s][v], bv[v], acc);
                 }
+            } else {
+                for (int s = 0; s < nsteps; ++s) {
+                    const int64_t c = (int64_t)s * STEP + q * VEC;
+                    TG gv[VEC], bv[VEC];
+                    if (arow_ok && c < a.n) {
+                        load_as<TG, VEC>(dC + arow * a.lddc + c, gv);
+                    } else {
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) acc = mfma4(gc[s][v], bv[v], acc);
+                        for (int v = 0; v < VEC; ++v) gv[v] = TG(0);
+                    }
+                    if (bok && c < a.n) {
+                        load_as<TB, VEC>(B + (int64_t)bc * a.ldb + c, bv);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v) bv[v] = TG(0);
+                    }
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) acc = mfma4(gv[v], bv[v], acc);
+                }
             }
-        } else {
-            for (int s = 0; s < nsteps; ++s) {
-                const int64_t c = (int64_t)s * STEP + q * VEC;
-                TG gv[VEC], bv[VEC];
-                if (arow_ok && c < a.n) {
-                    load_as<TG, VEC>(dC + arow * a.lddc + c, gv);
-                } else {
+            // lane (j, q) holds rows out_row(q, r) of tile c0 + j
+            if (bok) {
+                const int64_t blk = (int64_t)b0 + c0 + j;
 #pragma unroll
-                    for (int v = 0; v < VEC; ++v) gv[v] = TG(0);
+                for (int r = 0; r < 4; ++r) {
+                    const int i = out_row<TG>(q, r);
+                    const int32_t d = a.blk_src[pack_index(blk, i, a.half_pack)];
+                    if (d >= 0) dA[d] = acc[r];
                 }
-                if (bok && c < a.n) {
-                    load_as<TB, VEC>(B + (int64_t)bc * a.ldb + c, bv);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) bv[v] = TG(0);
-                }
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) acc = mfma4(gv[v], bv[v], acc);
-            }
-        }
-        // lane (j, q) holds rows out_row(q, r) of tile c0 + j
-        if (bok) {
-            const int64_t blk = (int64_t)b0 + c0 + j;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = out_row<TG>(q, r);
-                const int32_t d = a.blk_src[pack_index(blk, i, a.half_pack)];
-                if (d >= 0) dA[d] = acc[r];
             }
         }
     }
@@ -234,10 +255,11 @@ __device__ void sdd_bcsr_wave(const SddArgs& a, int64_t slot) {
 
 template <class TB, class TG, int VEC, int LPR, int BVEC, int NKR>
 __global__ __launch_bounds__(256) void k_sddmm(SddArgs a, uint32_t g_bcsr, uint32_t g_csr) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t bid = blockIdx.x;
     const int w = threadIdx.x >> 6;
     if (bid < g_bcsr) {
-        sdd_bcsr_wave<TB, TG, BVEC, NKR>(a, (int64_t)xcd_remap(bid, g_bcsr) * 4 + w);
+        sdd_bcsr_wg<TB, TG, BVEC, NKR>(a, (int64_t)xcd_remap(bid, g_bcsr), reinterpret_cast<TG*>(lds_raw));
     } else {
         sdd_csr_wave<TB, TG, VEC, LPR>(a, (int64_t)xcd_remap(bid - g_bcsr, g_csr) * 4 + w);
     }
@@ -264,9 +286,10 @@ int launch_sdd(const SubPlan& X, SddArgs a, hipStream_t s) {
     constexpr int R = 64 / LPR;
     const int64_t csr_waves = ceil_div(X.n_vrows, R);
     const uint32_t g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
-    const uint32_t g_bcsr = X.rb_bcsr ? pad8(ceil_div(X.rb_bcsr, 4)) : 0;
+    const uint32_t g_bcsr = X.rb_bcsr ? pad8(X.rb_bcsr) : 0;
     if (g_csr + g_bcsr == 0) return HSPMM_OK;
-    hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR>), dim3(g_bcsr + g_csr), dim3(256), 0, s, a, g_bcsr,
+    const size_t lds = g_bcsr ? (size_t)16 * (NKR * 4 * BVEC + 4) * sizeof(TG) : 0;
+    hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR>), dim3(g_bcsr + g_csr), dim3(256), lds, s, a, g_bcsr,
                        g_csr);
     HIP_LAUNCH_CHECK();
     return HSPMM_OK;

@@ -175,15 +175,73 @@ template <> struct AccOf<double> { typedef d4_t type; };
 template <class T> __device__ inline int out_row(int g, int r) { return 4 * g + r; }
 template <> __device__ inline int out_row<double>(int g, int r) { return g + 4 * r; }
 
+// One workgroup (4 waves) per (row block, column panel).  The row block's
+// K steps of 4 tiles are dealt round-robin to the 4 waves (step s -> wave
+// s % 4), so four independent gather streams run per row block; the four
+// partial 16 x PANEL tiles are then summed in a fixed order through LDS and
+// each wave stores one register row of the result.  The tile columns of up
+// to 16 rounds are fetched with one coalesced load and handed to the lanes
+// by a shuffle, so B loads never wait on an index load.
 template <class T, int VEC, int NL>
-__device__ void bcsr_wave_f(const BcsrArgs& a, const DenseArgs& d, int64_t wave) {
+struct StepRegs {
+    T av[2];
+    T bv[2][NL][VEC];
+};
+
+// Operands of this wave's two K steps in rounds r and r + 1 (zero-filled,
+// without memory access, past the row block's last tile).
+template <class T, int VEC, int NL>
+__device__ inline void load_steps(const T* __restrict__ vals, const T* __restrict__ B, int64_t ldb, int64_t n,
+                                  int b0, int cnt, int w, int kq, int lane, int colreg, int j0, int jend, int r,
+                                  int64_t cbase, StepRegs<T, VEC, NL>& o) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int rr = r + s;
+        const int step0 = 16 * rr + 4 * w;
+        const bool step_ok = rr < jend && step0 < cnt;
+        const bool ok = step_ok && step0 + kq < cnt;
+        const int bc = __shfl(colreg, (4 * (rr - j0) + kq) & 63, 64);
+        o.av[s] = step_ok ? vals[(int64_t)(b0 + step0) * 16 + lane] : T(0);
+#pragma unroll
+        for (int h = 0; h < NL; ++h) {
+            const int64_t col = cbase + (int64_t)h * 16 * VEC;
+            if (ok && col < n) {
+                load_vec<T, VEC>(B + (int64_t)bc * ldb + col, o.bv[s][h]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) o.bv[s][h][v] = T(0);
+            }
+        }
+    }
+}
+
+template <class T, class ACC, int VEC, int NL>
+__device__ inline void mfma_steps(const StepRegs<T, VEC, NL>& o, ACC (&acc)[VEC * NL]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int h = 0; h < NL; ++h)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[h * VEC + v] = mfma4(o.av[s], o.bv[s][h][v], acc[h * VEC + v]);
+}
+
+// One workgroup (4 waves) per (row block, column panel).  The row block's
+// K steps of 4 tiles are dealt round-robin to the 4 waves (step s -> wave
+// s % 4), so four independent gather streams run per row block; the four
+// partial 16 x PANEL tiles are then summed in a fixed order through LDS and
+// each wave stores one register row of the result.  The tile columns of up
+// to 16 rounds are fetched with one coalesced load and handed to the lanes
+// by a shuffle, so B loads never wait on an index load, and the loads of the
+// next two steps are in flight while the MFMAs of the current two run.
+template <class T, int VEC, int NL>
+__device__ void bcsr_wg_f(const BcsrArgs& a, const DenseArgs& d, int64_t unit, T* red) {
     typedef typename AccOf<T>::type acc_v;
     constexpr int PANEL = 16 * VEC * NL;
     constexpr int TILES = VEC * NL;
-    const int64_t slot = wave / a.n_panels;
-    if (slot >= a.n_rb) return;  // wave-uniform
-    const int panel = (int)(wave - slot * a.n_panels);
-    const int lane = threadIdx.x & 63, j = lane & 15, kq = lane >> 4;
+    const int64_t slot = unit / a.n_panels;
+    if (slot >= a.n_rb) return;  // uniform over the workgroup
+    const int panel = (int)(unit - slot * a.n_panels);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane & 15, kq = lane >> 4;
     const int rb = a.rb[slot];
     const int b0 = a.blk_ptr[slot];
     const int cnt = a.blk_cnt[slot];
@@ -194,48 +252,46 @@ __device__ void bcsr_wave_f(const BcsrArgs& a, const DenseArgs& d, int64_t wave)
 #pragma unroll
     for (int t = 0; t < TILES; ++t) acc[t] = acc_v{0, 0, 0, 0};
 
-    for (int c = 0; c < cnt; c += 8) {
-        // two K steps in flight
-        T av[2];
-        T bv[2][NL][VEC];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int kk = c + 4 * s + kq;
-            const bool ok = kk < cnt;
-            av[s] = (c + 4 * s < cnt) ? vals[(int64_t)(b0 + c + 4 * s) * 16 + lane] : T(0);
-            const int bc = ok ? a.blk_col[b0 + kk] : 0;
-#pragma unroll
-            for (int h = 0; h < NL; ++h) {
-                const int64_t col = cbase + (int64_t)h * 16 * VEC;
-                if (ok && col < d.n) {
-                    load_vec<T, VEC>(B + (int64_t)bc * d.ldb + col, bv[s][h]);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) bv[s][h][v] = T(0);
-                }
-            }
+    const int nrounds = (cnt + 15) >> 4;  // a round = 16 tiles = one step per wave
+    for (int j0 = 0; j0 < nrounds; j0 += 16) {
+        const int pre = 16 * (j0 + (lane >> 2)) + 4 * w + (lane & 3);
+        const int colreg = pre < cnt ? a.blk_col[b0 + pre] : 0;
+        const int jend = min(nrounds, j0 + 16);
+        StepRegs<T, VEC, NL> x, y;
+        load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend, j0, cbase, x);
+        for (int jr = j0; jr < jend; jr += 4) {
+            load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend, jr + 2, cbase, y);
+            mfma_steps<T, acc_v, VEC, NL>(x, acc);
+            if (jr + 2 >= jend) break;
+            load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend, jr + 4, cbase, x);
+            mfma_steps<T, acc_v, VEC, NL>(y, acc);
         }
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int h = 0; h < NL; ++h)
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) acc[h * VEC + v] = mfma4(av[s], bv[s][h][v], acc[h * VEC + v]);
     }
+    // fixed-order reduction of the four partial tiles
+#pragma unroll
+    for (int t = 0; t < TILES; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[((w * TILES + t) * 4 + r) * 64 + lane] = acc[t][r];
+    __syncthreads();
+    T sum[TILES];
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+        T x = red[((0 * TILES + t) * 4 + w) * 64 + lane];
+#pragma unroll
+        for (int v = 1; v < 4; ++v) x += red[((v * TILES + t) * 4 + w) * 64 + lane];
+        sum[t] = x;
+    }
+    const int64_t row = (int64_t)rb * 16 + out_row<T>(kq, w);
+    if (row >= d.m) return;
     const T sc = d.scale ? (T)d.scale[rb] : T(1);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t row = (int64_t)rb * 16 + out_row<T>(kq, r);
-        if (row >= d.m) continue;
+    for (int h = 0; h < NL; ++h) {
+        const int64_t col = cbase + (int64_t)h * 16 * VEC;
+        if (col >= d.n) continue;
+        T o[VEC];
 #pragma unroll
-        for (int h = 0; h < NL; ++h) {
-            const int64_t col = cbase + (int64_t)h * 16 * VEC;
-            if (col >= d.n) continue;
-            T o[VEC];
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) o[v] = acc[h * VEC + v][r] * sc;
-            store_vec<T, VEC>(static_cast<T*>(d.C) + row * d.ldc + col, o);
-        }
+        for (int v = 0; v < VEC; ++v) o[v] = sum[h * VEC + v] * sc;
+        store_vec<T, VEC>(static_cast<T*>(d.C) + row * d.ldc + col, o);
     }
 }
 
@@ -252,14 +308,18 @@ template <class T> struct V8Of;
 template <> struct V8Of<half_t> { typedef h8_t type; };
 template <> struct V8Of<bf16_t> { typedef b8_t type; };
 
+// Same workgroup scheme with 32-tile K steps (16x16x32 MFMA): step s of the
+// row block goes to wave s % 4.  Lane (j, g) gathers CPL columns of the 8 B
+// rows of tiles 8g..8g+7 of the step and transposes them in registers into
+// the K-major operand of each of the CPL column tiles.
 template <class T, int CPL>
-__device__ void bcsr_wave_h(const BcsrArgs& a, const DenseArgs& d, int64_t wave) {
+__device__ void bcsr_wg_h(const BcsrArgs& a, const DenseArgs& d, int64_t unit, float* red) {
     typedef typename V8Of<T>::type v8;
     constexpr int PANEL = 16 * CPL;
-    const int64_t slot = wave / a.n_panels;
+    const int64_t slot = unit / a.n_panels;
     if (slot >= a.n_rb) return;
-    const int panel = (int)(wave - slot * a.n_panels);
-    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    const int panel = (int)(unit - slot * a.n_panels);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane & 15, g = lane >> 4;
     const int rb = a.rb[slot];
     const int b0 = a.blk_ptr[slot];
     const int cnt = a.blk_cnt[slot];
@@ -271,15 +331,17 @@ __device__ void bcsr_wave_h(const BcsrArgs& a, const DenseArgs& d, int64_t wave)
 #pragma unroll
     for (int t = 0; t < CPL; ++t) acc[t] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-    for (int c = 0; c < cnt; c += 32) {
-        const v8 av = *reinterpret_cast<const v8*>(vals + ((int64_t)(b0 + c) * 16 + lane * 8));
+    for (int step0 = 32 * w; step0 < cnt; step0 += 128) {
+        // the 32 columns of this step: lane l holds tile step0 + (l & 31)
+        const int pre = step0 + (lane & 31);
+        const int colreg = pre < cnt ? a.blk_col[b0 + pre] : 0;
+        const v8 av = *reinterpret_cast<const v8*>(vals + ((int64_t)(b0 + step0) * 16 + lane * 8));
         T raw[8][CPL];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int kk = c + 8 * g + u;
-            const bool ok = kk < cnt && colok;
-            const int bc = ok ? a.blk_col[b0 + kk] : 0;
-            if (ok) {
+            const int kk = step0 + 8 * g + u;
+            const int bc = __shfl(colreg, 8 * g + u, 64);
+            if (kk < cnt && colok) {
                 load_vec<T, CPL>(B + (int64_t)bc * d.ldb + cbase, raw[u]);
             } else {
 #pragma unroll
@@ -294,27 +356,25 @@ __device__ void bcsr_wave_h(const BcsrArgs& a, const DenseArgs& d, int64_t wave)
             acc[t] = mfma32(av, bop, acc[t]);
         }
     }
-    const float sc = d.scale ? (float)d.scale[rb] : 1.0f;
-    if (!colok) return;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t row = (int64_t)rb * 16 + 4 * g + r;
-        if (row >= d.m) continue;
-        float o[CPL];
+    for (int t = 0; t < CPL; ++t)
 #pragma unroll
-        for (int t = 0; t < CPL; ++t) o[t] = acc[t][r] * sc;
-        float* dst = static_cast<float*>(d.C) + row * d.ldc + cbase;
-        if constexpr (CPL >= 4) {
+        for (int r = 0; r < 4; ++r) red[((w * CPL + t) * 4 + r) * 64 + lane] = acc[t][r];
+    __syncthreads();
+    float o[CPL];
 #pragma unroll
-            for (int q = 0; q < CPL; q += 4) {
-                float4 w = make_float4(o[q], o[q + 1], o[q + 2], o[q + 3]);
-                *reinterpret_cast<float4*>(dst + q) = w;
-            }
-        } else {
+    for (int t = 0; t < CPL; ++t) {
+        float x = red[((0 * CPL + t) * 4 + w) * 64 + lane];
 #pragma unroll
-            for (int t = 0; t < CPL; ++t) dst[t] = o[t];
-        }
+        for (int v = 1; v < 4; ++v) x += red[((v * CPL + t) * 4 + w) * 64 + lane];
+        o[t] = x;
     }
+    const int64_t row = (int64_t)rb * 16 + 4 * g + w;
+    if (row >= d.m || !colok) return;
+    const float sc = d.scale ? (float)d.scale[rb] : 1.0f;
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) o[t] *= sc;
+    store_vec<float, CPL>(static_cast<float*>(d.C) + row * d.ldc + cbase, o);
 }
 
 // ---------------------------------------------------------------------------
@@ -323,14 +383,15 @@ __device__ void bcsr_wave_h(const BcsrArgs& a, const DenseArgs& d, int64_t wave)
 template <class TV, class TB, class TC, int VEC, int LPR, int BV, int BNL>
 __global__ __launch_bounds__(256) void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseArgs da, uint32_t g_bcsr,
                                                 uint32_t g_csr) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t bid = blockIdx.x;
     const int w = threadIdx.x >> 6;
     if (bid < g_bcsr) {
-        const int64_t wave = (int64_t)xcd_remap(bid, g_bcsr) * 4 + w;
+        const int64_t unit = (int64_t)xcd_remap(bid, g_bcsr);
         if constexpr (sizeof(TV) == 2) {
-            bcsr_wave_h<TV, BV>(ba, da, wave);
+            bcsr_wg_h<TV, BV>(ba, da, unit, reinterpret_cast<float*>(lds_raw));
         } else {
-            bcsr_wave_f<TV, BV, BNL>(ba, da, wave);
+            bcsr_wg_f<TV, BV, BNL>(ba, da, unit, reinterpret_cast<TV*>(lds_raw));
         }
     } else {
         const int64_t wave = (int64_t)xcd_remap(bid - g_bcsr, g_csr) * 4 + w;
@@ -368,12 +429,16 @@ int launch_cfg(const SubPlan& X, const DenseArgs& d, hipStream_t s) {
                 X.blk_col.as<int32_t>(), X.blk_val.ptr, X.rb_bcsr, n_panels};
     constexpr int R = 64 / LPR;
     const int64_t csr_waves = ceil_div(X.n_vrows, R);
-    const int64_t bcsr_waves = X.rb_bcsr * (int64_t)n_panels;
+    const int64_t bcsr_units = X.rb_bcsr * (int64_t)n_panels;
     const uint32_t g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
-    const uint32_t g_bcsr = bcsr_waves ? pad8(ceil_div(bcsr_waves, 4)) : 0;
+    const uint32_t g_bcsr = bcsr_units ? pad8(bcsr_units) : 0;
     if (g_csr + g_bcsr == 0) return HSPMM_OK;
-    hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL>), dim3(g_bcsr + g_csr), dim3(256), 0, s, ca, ba,
-                       d, g_bcsr, g_csr);
+    // LDS of the BCSR reduction: 4 waves x tiles x 4 registers x 64 lanes
+    constexpr int TILES = (sizeof(TV) == 2) ? BV : BV * BNL;
+    constexpr size_t ACC_B = (sizeof(TV) == 8) ? 8 : 4;
+    const size_t lds = g_bcsr ? (size_t)4 * TILES * 4 * 64 * ACC_B : 0;
+    hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL>), dim3(g_bcsr + g_csr), dim3(256), lds, s, ca,
+                       ba, d, g_bcsr, g_csr);
     HIP_LAUNCH_CHECK();
     if (X.n_long > 0) {
         typedef typename Elem<TB>::acc_t acc_t;

@@ -1,0 +1,192 @@
+"""Backward of the hybrid SpMM on the GPU: dB = A^T dC through the device-built
+transposed plan and dA = SDDMM(dC, B) on A's pattern, against the FP64
+oracle, central finite differences and torch.autograd.gradcheck."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from tests.gpu_util import SPLITS, TOL, effective_vals, make_plan, quantized_dense, to_dev
+
+pytestmark = pytest.mark.gpu
+
+hs = pytest.importorskip("paper_2511_08158_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16, torch.bfloat16])
+@pytest.mark.parametrize("split", SPLITS)
+def test_backward_vs_oracle(dtype, split):
+    """dB and dA against the oracle; for FP16/BF16 the gradient is that of the
+    computed product (stored, quantised A; B as given), in FP32."""
+    print(f"backward dtype={dtype} split={split}", flush=True)
+    a = gen.random_csr(21, 301, 257, 0.06)
+    n = 72
+    g = np.random.default_rng(2)
+    B = g.standard_normal((a.k, n))
+    G = g.standard_normal((a.m, n))
+    plan = make_plan(hs, a, dtype, split, backward=True)
+    od = torch.float64 if dtype == torch.float64 else torch.float32
+    dB, dA = plan.backward(to_dev(B, dtype), to_dev(G, od))
+    torch.cuda.synchronize()
+    Aq = effective_vals(a.m, a.row_ptr, a.vals, dtype)
+    Bq = quantized_dense(B, dtype)
+    Gq = G.astype(np.float32).astype(np.float64) if od == torch.float32 else G
+    ref_db = oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, Aq, Gq)
+    ref_da = oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, Gq, Bq)
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    assert oracle.rel_err(dB.double().cpu().numpy(), ref_db) <= tol
+    assert oracle.rel_err(dA.double().cpu().numpy(), ref_da) <= tol
+    # end-to-end against the unquantised problem
+    assert oracle.rel_err(dB.double().cpu().numpy(),
+                          oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, G)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_backward_integer_bitwise(split):
+    a = gen.random_csr(3, 190, 170, 0.07, dist="int")
+    g = np.random.default_rng(0)
+    B = g.integers(-3, 4, (a.k, 40)).astype(float)
+    G = g.integers(-3, 4, (a.m, 40)).astype(float)
+    plan = make_plan(hs, a, torch.float32, split, backward=True)
+    dB, dA = plan.backward(to_dev(B, torch.float32), to_dev(G, torch.float32))
+    torch.cuda.synchronize()
+    assert np.array_equal(dB.double().cpu().numpy(), oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, G))
+    assert np.array_equal(dA.double().cpu().numpy(), oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, G, B))
+
+
+def test_transposed_format_equals_cpu_transpose():
+    from oracle import loops_ref as L
+    a = gen.random_csr(4, 120, 90, 0.1)
+    plan = make_plan(hs, a, torch.float32, "csr", backward=True)
+    ptr, col, val, perm = L.transpose_ref(a.m, a.k, a.row_ptr, a.col_idx, a.vals)
+    assert np.array_equal(plan.export("csr_ptr", which=1), ptr)
+    assert np.array_equal(plan.export("csr_col", which=1), col)
+    assert np.array_equal(plan.export("csr_val", which=1), val.astype(np.float32))
+
+
+def test_backward_without_transposed_plan_is_an_error():
+    a = gen.random_csr(1, 40, 40, 0.1)
+    plan = make_plan(hs, a, torch.float32, "auto", backward=False)
+    B = to_dev(np.ones((40, 4)), torch.float32)
+    with pytest.raises(hs.HspmmError) as e:
+        plan.backward(B, to_dev(np.ones((40, 4)), torch.float32), need_dB=True, need_dA=False)
+    assert e.value.code == -4
+    # dA alone needs no transposed plan
+    _, dA = plan.backward(B, to_dev(np.ones((40, 4)), torch.float32), need_dB=False, need_dA=True)
+    torch.cuda.synchronize()
+    assert dA.shape[0] == a.nnz
+
+
+def test_gradcheck_tiny_fp64():
+    a = gen.random_csr(7, 18, 14, 0.3)
+    dev = torch.device("cuda:0")
+    vals = torch.tensor(a.vals, device=dev, requires_grad=True)
+    B = torch.tensor(np.random.default_rng(1).standard_normal((a.k, 5)), device=dev, requires_grad=True)
+    for split in SPLITS:
+        plan = hs.Plan(a.row_ptr, a.col_idx, vals.detach(), (a.m, a.k), compute=torch.float64, split=split,
+                       backward=True)
+        assert torch.autograd.gradcheck(lambda v, b: hs.spmm(plan, v, b), (vals, B), eps=1e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("split", SPLITS)
+@pytest.mark.parametrize("n", [64, 128])
+def test_gcn_subgraph_parity(dtype, split, n):
+    """The FD subgraph (dense-ish BFS ball, one 497-entry row) through every
+    split: forward and both gradients against the oracle."""
+    full, _ = gen.config4()
+    sub = gen.config4_fd_subgraph(full, 512)
+    g = np.random.default_rng(11)
+    X = g.standard_normal((sub.k, n))
+    G = g.standard_normal((sub.m, n))
+    plan = make_plan(hs, sub, dtype, split, backward=True)
+    od = torch.float64 if dtype == torch.float64 else torch.float32
+    C = plan.run(to_dev(X, dtype))
+    dX, dA = plan.backward(to_dev(X, dtype), to_dev(G, od))
+    torch.cuda.synchronize()
+    e = (oracle.rel_err(C.double().cpu().numpy(), oracle.spmm(sub.m, sub.k, sub.row_ptr, sub.col_idx, sub.vals, X)),
+         oracle.rel_err(dX.double().cpu().numpy(), oracle.spmm_t(sub.m, sub.k, sub.row_ptr, sub.col_idx, sub.vals, G)),
+         oracle.rel_err(dA.double().cpu().numpy(), oracle.sddmm(sub.m, sub.k, sub.row_ptr, sub.col_idx, G, X)))
+    print(f"subgraph {dtype} {split} n={n}: C {e[0]:.2e} dX {e[1]:.2e} dA {e[2]:.2e} info {plan.info()}", flush=True)
+    assert max(e) <= TOL[dtype]
+
+
+def test_finite_differences_gcn_subgraph():
+    """Central differences (eps 1e-3, FP64) on the 512-node BFS subgraph of
+    the GCN graph.  L = <A(vals) X, G> is linear in X and in vals, so the
+    differences are exact up to rounding."""
+    full, _ = gen.config4()
+    sub = gen.config4_fd_subgraph(full, 512)
+    dev = torch.device("cuda:0")
+    g = np.random.default_rng(11)
+    X = g.standard_normal((sub.k, 128))
+    G = g.standard_normal((sub.m, 128))
+    plan = hs.Plan(sub.row_ptr, sub.col_idx, to_dev(sub.vals), (sub.m, sub.k), compute=torch.float64,
+                   split="auto", backward=True)
+    Xd, Gd = to_dev(X), to_dev(G)
+    dX, dA = plan.backward(Xd, Gd)
+
+    def loss(vals=None, Xv=None):
+        # every evaluation sets the values it needs (A itself unless perturbed)
+        plan.update_values(to_dev(sub.vals if vals is None else vals))
+        C = plan.run(Xd if Xv is None else Xv)
+        return float((C * Gd).sum())
+
+    eps = 1e-3
+    tol = 1e-8
+    # 8 random directions over all coordinates
+    for d in range(8):
+        D = torch.tensor(g.standard_normal(X.shape), device=dev)
+        fd = (loss(Xv=Xd + eps * D) - loss(Xv=Xd - eps * D)) / (2 * eps)
+        an = float((dX * D).sum())
+        assert abs(fd - an) <= tol * max(1.0, abs(an))
+        dv = g.standard_normal(sub.nnz)
+        fd = (loss(vals=sub.vals + eps * dv) - loss(vals=sub.vals - eps * dv)) / (2 * eps)
+        an = float(np.dot(dA.cpu().numpy(), dv))
+        assert abs(fd - an) <= tol * max(1.0, abs(an))
+    plan.update_values(to_dev(sub.vals))
+    # 64 seeded single entries each
+    for e in g.choice(sub.nnz, 64, replace=False):
+        dv = np.zeros(sub.nnz)
+        dv[e] = 1.0
+        fd = (loss(vals=sub.vals + eps * dv) - loss(vals=sub.vals - eps * dv)) / (2 * eps)
+        assert abs(fd - float(dA[e])) <= tol * max(1.0, abs(fd))
+    plan.update_values(to_dev(sub.vals))
+    for idx in g.choice(X.size, 64, replace=False):
+        i, j = divmod(int(idx), X.shape[1])
+        D = torch.zeros_like(Xd)
+        D[i, j] = 1.0
+        fd = (loss(Xv=Xd + eps * D) - loss(Xv=Xd - eps * D)) / (2 * eps)
+        assert abs(fd - float(dX[i, j])) <= tol * max(1.0, abs(fd))
+    # and the gradient agrees with the oracle
+    ref_dx = oracle.spmm_t(sub.m, sub.k, sub.row_ptr, sub.col_idx, sub.vals, G)
+    assert oracle.rel_err(dX.cpu().numpy(), ref_dx) <= 1e-12
+
+
+def test_autograd_training_step_gcn_layer():
+    """spmm inside a tiny two-layer graph network: gradients of a dense
+    weight through the SpMM match the same network evaluated with the
+    oracle's products on the CPU."""
+    a = gen.random_csr(13, 257, 257, 0.03)
+    dev = torch.device("cuda:0")
+    g = np.random.default_rng(3)
+    X = torch.tensor(g.standard_normal((257, 16)), device=dev)
+    W = torch.tensor(g.standard_normal((16, 8)), device=dev, requires_grad=True)
+    plan = hs.Plan(a.row_ptr, a.col_idx, to_dev(a.vals), (a.m, a.k), compute=torch.float64, backward=True)
+    vals = to_dev(a.vals)
+    H = torch.relu(hs.spmm(plan, vals, X @ W))
+    loss = (H ** 2).sum()
+    loss.backward()
+    # CPU reference with dense matrices
+    Ad = torch.tensor(a.to_scipy().toarray())
+    Wc = W.detach().cpu().clone().requires_grad_(True)
+    Hc = torch.relu(Ad @ (X.cpu() @ Wc))
+    (Hc ** 2).sum().backward()
+    assert torch.allclose(W.grad.cpu(), Wc.grad, rtol=1e-11, atol=1e-11)
