@@ -174,6 +174,38 @@ typedef enum {
 int hybrid_spmm_export(hspmm_plan_t p, int32_t which, int32_t field, void* dst,
                        int64_t capacity, int64_t* bytes);
 
+/* Calibration of the workgroup partition of the fused forward launch, the
+ * analogue of the thread split (t_neon, t_sme) of Sec. 3.5: the forward is
+ * timed on `stream` at a candidate set of partitions (x, y) = (workgroups
+ * of the CSR-part, workgroups of the BCSR-part, both in units of 8) with
+ * x + y <= T, T = the workgroups the GPU holds at once / 8; Eq. 2
+ * perf(x, y) = a0 + a1 x + a2 y + a3 x^2 + a4 y^2 (GFLOP/s) is fitted by
+ * least squares (terms of an empty part dropped) and Eq. 3 picks the
+ * argmax over all integer x + y <= T.  The chosen partition is applied to
+ * later runs if it measures at least as fast as the default launch (one
+ * workgroup per work unit); otherwise the default is kept.
+ *   B, C, n, ldb, ldc: as in hybrid_spmm_run (C is overwritten);
+ *   reps: timed launches per candidate (>= 1); info: host output.
+ * Host-synchronous.  Errors: ARG, HIP. */
+#define HSPMM_CALIB_MAX 32
+typedef struct {
+    uint32_t struct_size;            /* must be sizeof(hspmm_calib_info) */
+    int32_t T;                       /* partition units available (x + y <= T) */
+    int32_t x_max, y_max;            /* units each part can use (0: part empty) */
+    int32_t n_candidates;
+    int32_t cand_x[HSPMM_CALIB_MAX]; /* CSR-part workgroups / 8 */
+    int32_t cand_y[HSPMM_CALIB_MAX]; /* BCSR-part workgroups / 8 */
+    double cand_gflops[HSPMM_CALIB_MAX];
+    double coef[5];                  /* a0..a4 of Eq. 2 (dropped terms are 0) */
+    int32_t best_x, best_y;          /* Eq. 3 argmax */
+    double best_gflops;              /* measured at (best_x, best_y) */
+    double default_gflops;           /* measured with the default launch */
+    int32_t applied;                 /* 1: (best_x, best_y) is used by later runs */
+} hspmm_calib_info;
+
+int hybrid_spmm_calibrate(hspmm_plan_t p, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc,
+                          int32_t reps, hspmm_calib_info* info, void* stream);
+
 /* Release the plan and all its device memory (NULL-safe). */
 void hybrid_spmm_destroy(hspmm_plan_t p);
 

@@ -201,12 +201,15 @@ def quad_eval(coef, x, y):
     return a0 + a1 * x + a2 * y + a3 * x * x + a4 * y * y
 
 
-def argmax_ref(coef, T, x_min=0, y_min=0):
-    """argmax of the quadratic over integers x >= x_min, y >= y_min,
-    1 <= x + y <= T; ties go to the first pair in (x, y) lexicographic order."""
+def argmax_ref(coef, T, x_min=0, y_min=0, x_max=None, y_max=None):
+    """argmax of the quadratic over integers x_min <= x <= x_max,
+    y_min <= y <= y_max, 1 <= x + y <= T (bounds default to T); ties go to
+    the first pair in (x, y) lexicographic order."""
+    x_max = T if x_max is None else x_max
+    y_max = T if y_max is None else y_max
     best, arg = -math.inf, None
-    for x in range(x_min, T + 1):
-        for y in range(y_min, T + 1 - x):
+    for x in range(x_min, min(T, x_max) + 1):
+        for y in range(y_min, min(T - x, y_max) + 1):
             if x + y < 1:
                 continue
             v = quad_eval(coef, x, y)

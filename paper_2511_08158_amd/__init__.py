@@ -157,6 +157,23 @@ class Plan:
         _check(library().hybrid_spmm_update_values(self.handle, _ptr(v), DTYPES[v.dtype], _stream()))
         self._vals_key = (vals.data_ptr(), vals._version)
 
+    def calibrate(self, B, reps: int = 5) -> dict:
+        """Fit the quadratic model (Eq. 2) of forward throughput over
+        workgroup partitions of the two parts and apply its argmax (Eq. 3)
+        when it measures at least as fast as the default launch."""
+        B = self._dense(B, self.k, "B")
+        n = B.shape[1]
+        C = torch.empty((self.m, n), dtype=self.out_dtype, device=self.device)
+        ci = _lib.CalibInfo()
+        ci.struct_size = ctypes.sizeof(_lib.CalibInfo)
+        _check(library().hybrid_spmm_calibrate(self.handle, n, _ptr(B), B.stride(0) if self.k else n,
+                                               _ptr(C), n, int(reps), ctypes.byref(ci), _stream()))
+        k = ci.n_candidates
+        return {"T": ci.T, "x_max": ci.x_max, "y_max": ci.y_max, "cand_x": list(ci.cand_x[:k]), "cand_y": list(ci.cand_y[:k]),
+                "cand_gflops": list(ci.cand_gflops[:k]), "coef": list(ci.coef),
+                "best": (ci.best_x, ci.best_y), "best_gflops": ci.best_gflops,
+                "default_gflops": ci.default_gflops, "applied": bool(ci.applied)}
+
     # -- inspection --------------------------------------------------------
     def info(self) -> dict:
         i = _lib.PlanInfo()

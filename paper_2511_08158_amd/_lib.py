@@ -63,10 +63,30 @@ class PlanInfo(ctypes.Structure):
     ]
 
 
+CALIB_MAX = 32
+
+
+class CalibInfo(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("T", ctypes.c_int32),
+        ("x_max", ctypes.c_int32), ("y_max", ctypes.c_int32),
+        ("n_candidates", ctypes.c_int32),
+        ("cand_x", ctypes.c_int32 * CALIB_MAX),
+        ("cand_y", ctypes.c_int32 * CALIB_MAX),
+        ("cand_gflops", ctypes.c_double * CALIB_MAX),
+        ("coef", ctypes.c_double * 5),
+        ("best_x", ctypes.c_int32), ("best_y", ctypes.c_int32),
+        ("best_gflops", ctypes.c_double),
+        ("default_gflops", ctypes.c_double),
+        ("applied", ctypes.c_int32),
+    ]
+
+
 EXPORTED = [
     "hybrid_spmm_plan", "hybrid_spmm_run", "hybrid_spmm_backward", "hybrid_spmm_update_values",
     "hybrid_spmm_plan_info", "hybrid_spmm_export", "hybrid_spmm_destroy",
-    "hybrid_spmm_last_error", "hybrid_spmm_version",
+    "hybrid_spmm_last_error", "hybrid_spmm_version", "hybrid_spmm_calibrate",
 ]
 
 _lib = None
@@ -88,10 +108,12 @@ def load():
     L.hybrid_spmm_update_values.argtypes = [vp, vp, i32, vp]
     L.hybrid_spmm_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.hybrid_spmm_export.argtypes = [vp, i32, i32, vp, i64, ctypes.POINTER(i64)]
+    L.hybrid_spmm_calibrate.argtypes = [vp, i64, vp, i64, vp, i64, i32, ctypes.POINTER(CalibInfo), vp]
     L.hybrid_spmm_destroy.argtypes = [vp]
     L.hybrid_spmm_destroy.restype = None
     for f in (L.hybrid_spmm_plan, L.hybrid_spmm_run, L.hybrid_spmm_backward,
-              L.hybrid_spmm_update_values, L.hybrid_spmm_plan_info, L.hybrid_spmm_export):
+              L.hybrid_spmm_update_values, L.hybrid_spmm_plan_info, L.hybrid_spmm_export,
+              L.hybrid_spmm_calibrate):
         f.restype = ctypes.c_int
     L.hybrid_spmm_last_error.restype = ctypes.c_char_p
     L.hybrid_spmm_version.restype = ctypes.c_char_p

@@ -1,6 +1,7 @@
 // C ABI of the hspmm library (include/hspmm.h).
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <new>
 
 #include "plan.h"
@@ -59,6 +60,14 @@ int Allocator::alloc(DevBuf& b, size_t nbytes) {
     in_use += nbytes;
     peak = std::max(peak, in_use);
     return HSPMM_OK;
+}
+
+int xcd_remap_mode() {
+    static const int mode = [] {
+        const char* e = getenv("HSPMM_XCD_REMAP");
+        return (e && e[0] == '0') ? 0 : 1;
+    }();
+    return mode;
 }
 
 int ensure_ws(Plan& p, size_t bytes) {
@@ -298,6 +307,19 @@ int hybrid_spmm_export(hspmm_plan_t h, int32_t which, int32_t field, void* dst, 
     *bytes = (int64_t)buf.size();
     if (dst && capacity >= (int64_t)buf.size() && !buf.empty()) memcpy(dst, buf.data(), buf.size());
     return HSPMM_OK;
+}
+
+int hybrid_spmm_calibrate(hspmm_plan_t h, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc,
+                          int32_t reps, hspmm_calib_info* info, void* stream) {
+    clear_error();
+    if (!h || !info) return fail(HSPMM_ERR_ARG, "NULL argument");
+    if (info->struct_size != sizeof(hspmm_calib_info))
+        return fail(HSPMM_ERR_ARG, "hspmm_calib_info.struct_size mismatch");
+    Plan& p = h->p;
+    if (n <= 0 || reps < 1) return fail(HSPMM_ERR_ARG, "n and reps must be positive");
+    if (!C || (p.k > 0 && !B)) return fail(HSPMM_ERR_ARG, "B or C is NULL");
+    if (ldc < n || (p.k > 0 && ldb < n)) return fail(HSPMM_ERR_ARG, "leading dimension smaller than n");
+    return calibrate(p, n, B, ldb, C, ldc, reps, info, static_cast<hipStream_t>(stream));
 }
 
 void hybrid_spmm_destroy(hspmm_plan_t h) {

@@ -187,11 +187,14 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 // Workgroup -> XCD mapping.  The dispatcher hands consecutive workgroups to
 // the 8 XCDs in turn; remapping id -> (id % 8) * (G / 8) + id / 8 gives each
 // XCD a contiguous range of logical tiles so neighbouring tiles share its L2.
-// G must be a multiple of 8 (launchers pad the grid).
-__device__ inline uint32_t xcd_remap(uint32_t id, uint32_t G) {
+// G must be a multiple of 8 (launchers pad the grid).  mode 0 keeps the
+// dispatch order (tuning knob HSPMM_XCD_REMAP=0).
+__device__ inline uint32_t xcd_remap(uint32_t id, uint32_t G, int mode) {
+    if (!mode) return id;
     const uint32_t per = G >> 3;
     return (id & 7u) * per + (id >> 3);
 }
+int xcd_remap_mode();
 
 constexpr int kNumXcd = 8;
 

@@ -56,42 +56,48 @@ int64_t eq1_boundary(int64_t r_total, double tp_csr, double t_csr, double tp_bcs
 }
 
 // Normal equations solved by Gaussian elimination with partial pivoting on
-// the 5 x 5 system (A^T A) a = A^T perf.
+// the system of the active terms, (A^T A) a = A^T perf.
 bool fit_quadratic(const std::vector<double>& x, const std::vector<double>& y,
-                   const std::vector<double>& perf, double a[5]) {
+                   const std::vector<double>& perf, double a[5], unsigned mask) {
     const size_t n = x.size();
-    if (n < 5 || y.size() != n || perf.size() != n) return false;
+    int idx[5], k = 0;
+    for (int i = 0; i < 5; ++i)
+        if (mask & (1u << i)) idx[k++] = i;
+    for (int i = 0; i < 5; ++i) a[i] = 0.0;
+    if (k == 0 || n < (size_t)k || y.size() != n || perf.size() != n) return false;
     double M[5][6] = {};
     for (size_t s = 0; s < n; ++s) {
-        const double row[5] = {1.0, x[s], y[s], x[s] * x[s], y[s] * y[s]};
-        for (int i = 0; i < 5; ++i) {
-            for (int j = 0; j < 5; ++j) M[i][j] += row[i] * row[j];
-            M[i][5] += row[i] * perf[s];
+        const double full[5] = {1.0, x[s], y[s], x[s] * x[s], y[s] * y[s]};
+        for (int i = 0; i < k; ++i) {
+            for (int j = 0; j < k; ++j) M[i][j] += full[idx[i]] * full[idx[j]];
+            M[i][k] += full[idx[i]] * perf[s];
         }
     }
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < k; ++c) {
         int p = c;
-        for (int r = c + 1; r < 5; ++r)
+        for (int r = c + 1; r < k; ++r)
             if (std::fabs(M[r][c]) > std::fabs(M[p][c])) p = r;
         if (std::fabs(M[p][c]) < 1e-300) return false;
         if (p != c)
-            for (int j = 0; j < 6; ++j) std::swap(M[p][j], M[c][j]);
-        for (int r = 0; r < 5; ++r) {
+            for (int j = 0; j <= k; ++j) std::swap(M[p][j], M[c][j]);
+        for (int r = 0; r < k; ++r) {
             if (r == c) continue;
             const double f = M[r][c] / M[c][c];
-            for (int j = c; j < 6; ++j) M[r][j] -= f * M[c][j];
+            for (int j = c; j <= k; ++j) M[r][j] -= f * M[c][j];
         }
     }
-    for (int i = 0; i < 5; ++i) a[i] = M[i][5] / M[i][i];
+    for (int i = 0; i < k; ++i) a[idx[i]] = M[i][k] / M[i][i];
     return true;
 }
 
-void argmax_quadratic(const double a[5], int T, int* bx, int* by) {
+void argmax_quadratic(const double a[5], int T, int* bx, int* by, int xlo, int xhi, int ylo, int yhi) {
+    if (xhi < 0) xhi = T;
+    if (yhi < 0) yhi = T;
     double best = -std::numeric_limits<double>::infinity();
-    *bx = 0;
-    *by = 0;
-    for (int x = 0; x <= T; ++x)
-        for (int y = 0; x + y <= T; ++y) {
+    *bx = xlo;
+    *by = ylo;
+    for (int x = xlo; x <= xhi; ++x)
+        for (int y = ylo; y <= yhi && x + y <= T; ++y) {
             if (x + y < 1) continue;
             const double v = a[0] + a[1] * x + a[2] * y + a[3] * x * x + a[4] * y * y;
             if (v > best) {

@@ -41,10 +41,13 @@ int64_t eq1_boundary(int64_t r_total, double tp_csr, double t_csr, double tp_bcs
                      int br);
 
 // Eq. 2: least-squares coefficients a0..a4 of perf = a0 + a1 x + a2 y + a3 x^2 + a4 y^2.
+// Terms whose mask bit (1 << i) is clear are left out of the fit (a[i] = 0),
+// e.g. the x terms when one part is empty.
 bool fit_quadratic(const std::vector<double>& x, const std::vector<double>& y,
-                   const std::vector<double>& perf, double a[5]);
-// Eq. 3: argmax over integers x >= 0, y >= 0, 1 <= x + y <= T (first in
-// lexicographic order on ties).
-void argmax_quadratic(const double a[5], int T, int* x, int* y);
+                   const std::vector<double>& perf, double a[5], unsigned mask = 0x1f);
+// Eq. 3: argmax over integers x in [xlo, xhi], y in [ylo, yhi] with
+// 1 <= x + y <= T (first in lexicographic order on ties).
+void argmax_quadratic(const double a[5], int T, int* x, int* y, int xlo = 0, int xhi = -1, int ylo = 0,
+                      int yhi = -1);
 
 }  // namespace hspmm

@@ -37,6 +37,10 @@ struct SubPlan {
 
     DevBuf scale;                 // double [nrb] (scaled sub-plans only)
 
+    // workgroup partition of the fused launch (0 = one workgroup per work
+    // unit); set by calibration
+    int32_t part_csr = 0, part_bcsr = 0;
+
     int64_t bytes() const;
 };
 
@@ -66,13 +70,22 @@ struct Plan {
 // vals/row_of helpers shared by the plan build and update_values
 int pack_values(Plan& p, const void* vals, int vals_dtype, hipStream_t s);
 
+// geometry of a forward launch (filled instead of launching when requested)
+struct LaunchQuery {
+    uint32_t g_csr = 0, g_bcsr = 0;  // default workgroups of each part
+    int wg_per_cu = 0;               // resident workgroups per CU for the kernel
+};
+
 // forward product of one sub-plan: C = X * B
 int launch_forward(Plan& p, SubPlan& X, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc,
-                   hipStream_t s);
+                   hipStream_t s, LaunchQuery* q = nullptr);
 // SDDMM on A's pattern: dA_canon[c] (or dA_in[e] via canon_of_orig)
 int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dA,
                  hipStream_t s);
 int ensure_ws(Plan& p, size_t bytes);
+
+int calibrate(Plan& p, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc, int reps,
+              hspmm_calib_info* info, hipStream_t s);
 
 int build_plan(Plan& p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int vals_dtype,
                hipStream_t s);

@@ -491,6 +491,9 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
             lcnt.push_back(c);
         }
     }
+    // short rows in row order: neighbouring rows share gathered rows of B
+    // (ordering them by length to even out lane groups measured slower on
+    // every workload, banded and power-law alike)
     for (int64_t r = 0; r < X.rows_csr; ++r) {
         const int32_t lo = cptr[r], hi = cptr[r + 1];
         if (hi - lo > seg) continue;

@@ -203,22 +203,34 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
             if (c0 >= cnt) break;
             const bool bok = c0 + j < cnt;
             const int bc = __shfl(colreg, (16 * (it - it0) + j) & 63, 64);
+            // destinations of this lane's four results, fetched before the
+            // products so their latency overlaps the gathers
+            int32_t dst[4];
+            {
+                const int64_t blk = (int64_t)b0 + c0 + j;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    dst[r] = bok ? a.blk_src[pack_index(blk, out_row<TG>(q, r), a.half_pack)] : -1;
+            }
             acc_v acc = acc_v{0, 0, 0, 0};
             if (cached) {
+                // all gathers of the chunk first, then the products
+                TG bv[NKR][VEC];
 #pragma unroll
                 for (int s = 0; s < NKR; ++s) {
-                    if (s >= nsteps) break;
                     const int64_t c = (int64_t)s * STEP + q * VEC;
-                    TG bv[VEC];
-                    if (bok && c < a.n) {
-                        load_as<TB, VEC>(B + (int64_t)bc * a.ldb + c, bv);
+                    if (s < nsteps && bok && c < a.n) {
+                        load_as<TB, VEC>(B + (int64_t)bc * a.ldb + c, bv[s]);
                     } else {
 #pragma unroll
-                        for (int v = 0; v < VEC; ++v) bv[v] = TG(0);
+                        for (int v = 0; v < VEC; ++v) bv[s][v] = TG(0);
                     }
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) acc = mfma4(gc[s][v], bv[v], acc);
                 }
+#pragma unroll
+                for (int s = 0; s < NKR; ++s)
+                    if (s < nsteps)
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v) acc = mfma4(gc[s][v], bv[s][v], acc);
             } else {
                 for (int s = 0; s < nsteps; ++s) {
                     const int64_t c = (int64_t)s * STEP + q * VEC;
@@ -240,28 +252,27 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
                 }
             }
             // lane (j, q) holds rows out_row(q, r) of tile c0 + j
-            if (bok) {
-                const int64_t blk = (int64_t)b0 + c0 + j;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = out_row<TG>(q, r);
-                    const int32_t d = a.blk_src[pack_index(blk, i, a.half_pack)];
-                    if (d >= 0) dA[d] = acc[r];
-                }
-            }
+            for (int r = 0; r < 4; ++r)
+                if (dst[r] >= 0) dA[dst[r]] = acc[r];
         }
     }
 }
 
-template <class TB, class TG, int VEC, int LPR, int BVEC, int NKR>
-__global__ __launch_bounds__(256) void k_sddmm(SddArgs a, uint32_t g_bcsr, uint32_t g_csr) {
+// DO_CSR / DO_BCSR compile out a part the plan does not have (register
+// footprint of a one-part launch).
+template <class TB, class TG, int VEC, int LPR, int BVEC, int NKR, bool DO_CSR, bool DO_BCSR>
+__global__ __launch_bounds__(256) void k_sddmm(SddArgs a, uint32_t g_bcsr, uint32_t g_csr, int remap) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t bid = blockIdx.x;
     const int w = threadIdx.x >> 6;
     if (bid < g_bcsr) {
-        sdd_bcsr_wg<TB, TG, BVEC, NKR>(a, (int64_t)xcd_remap(bid, g_bcsr), reinterpret_cast<TG*>(lds_raw));
+        if constexpr (DO_BCSR)
+            sdd_bcsr_wg<TB, TG, BVEC, NKR>(a, (int64_t)xcd_remap(bid, g_bcsr, remap),
+                                           reinterpret_cast<TG*>(lds_raw));
     } else {
-        sdd_csr_wave<TB, TG, VEC, LPR>(a, (int64_t)xcd_remap(bid - g_bcsr, g_csr) * 4 + w);
+        if constexpr (DO_CSR)
+            sdd_csr_wave<TB, TG, VEC, LPR>(a, (int64_t)xcd_remap(bid - g_bcsr, g_csr, remap) * 4 + w);
     }
 }
 
@@ -289,8 +300,18 @@ int launch_sdd(const SubPlan& X, SddArgs a, hipStream_t s) {
     const uint32_t g_bcsr = X.rb_bcsr ? pad8(X.rb_bcsr) : 0;
     if (g_csr + g_bcsr == 0) return HSPMM_OK;
     const size_t lds = g_bcsr ? (size_t)16 * (NKR * 4 * BVEC + 4) * sizeof(TG) : 0;
-    hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR>), dim3(g_bcsr + g_csr), dim3(256), lds, s, a, g_bcsr,
-                       g_csr);
+    const dim3 grid(g_bcsr + g_csr), block(256);
+    const int rm = xcd_remap_mode();
+    if (g_bcsr && g_csr) {
+        hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, true, true>), grid, block, lds, s, a, g_bcsr, g_csr,
+                           rm);
+    } else if (g_csr) {
+        hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, true, false>), grid, block, 0, s, a, g_bcsr, g_csr,
+                           rm);
+    } else {
+        hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, false, true>), grid, block, lds, s, a, g_bcsr,
+                           g_csr, rm);
+    }
     HIP_LAUNCH_CHECK();
     return HSPMM_OK;
 }

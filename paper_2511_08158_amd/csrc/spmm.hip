@@ -182,26 +182,33 @@ template <> __device__ inline int out_row<double>(int g, int r) { return g + 4 *
 // each wave stores one register row of the result.  The tile columns of up
 // to 16 rounds are fetched with one coalesced load and handed to the lanes
 // by a shuffle, so B loads never wait on an index load.
+// Operands of SB consecutive K steps of one wave.
+#ifndef HSPMM_STEP_BATCH
+#define HSPMM_STEP_BATCH 1
+#endif
+constexpr int kStepBatch = HSPMM_STEP_BATCH;
 template <class T, int VEC, int NL>
 struct StepRegs {
-    T av[2];
-    T bv[2][NL][VEC];
+    T av[kStepBatch];
+    T bv[kStepBatch][NL][VEC];
 };
 
-// Operands of this wave's two K steps in rounds r and r + 1 (zero-filled,
-// without memory access, past the row block's last tile).
+// Operands of this wave's K steps in rounds r .. r + kStepBatch - 1
+// (zero-filled, without memory access, past the row block's last tile).
+// The packed values are read once, so they bypass the caches' reuse
+// policy (non-temporal) and leave L2 to the gathered rows of B.
 template <class T, int VEC, int NL>
 __device__ inline void load_steps(const T* __restrict__ vals, const T* __restrict__ B, int64_t ldb, int64_t n,
                                   int b0, int cnt, int w, int kq, int lane, int colreg, int j0, int jend, int r,
                                   int64_t cbase, StepRegs<T, VEC, NL>& o) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < kStepBatch; ++s) {
         const int rr = r + s;
         const int step0 = 16 * rr + 4 * w;
         const bool step_ok = rr < jend && step0 < cnt;
         const bool ok = step_ok && step0 + kq < cnt;
         const int bc = __shfl(colreg, (4 * (rr - j0) + kq) & 63, 64);
-        o.av[s] = step_ok ? vals[(int64_t)(b0 + step0) * 16 + lane] : T(0);
+        o.av[s] = step_ok ? __builtin_nontemporal_load(vals + (int64_t)(b0 + step0) * 16 + lane) : T(0);
 #pragma unroll
         for (int h = 0; h < NL; ++h) {
             const int64_t col = cbase + (int64_t)h * 16 * VEC;
@@ -218,7 +225,7 @@ __device__ inline void load_steps(const T* __restrict__ vals, const T* __restric
 template <class T, class ACC, int VEC, int NL>
 __device__ inline void mfma_steps(const StepRegs<T, VEC, NL>& o, ACC (&acc)[VEC * NL]) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+    for (int s = 0; s < kStepBatch; ++s)
 #pragma unroll
         for (int h = 0; h < NL; ++h)
 #pragma unroll
@@ -232,7 +239,7 @@ __device__ inline void mfma_steps(const StepRegs<T, VEC, NL>& o, ACC (&acc)[VEC 
 // each wave stores one register row of the result.  The tile columns of up
 // to 16 rounds are fetched with one coalesced load and handed to the lanes
 // by a shuffle, so B loads never wait on an index load, and the loads of the
-// next two steps are in flight while the MFMAs of the current two run.
+// next kStepBatch steps are in flight while the MFMAs of the current ones run.
 template <class T, int VEC, int NL>
 __device__ void bcsr_wg_f(const BcsrArgs& a, const DenseArgs& d, int64_t unit, T* red) {
     typedef typename AccOf<T>::type acc_v;
@@ -259,27 +266,36 @@ __device__ void bcsr_wg_f(const BcsrArgs& a, const DenseArgs& d, int64_t unit, T
         const int jend = min(nrounds, j0 + 16);
         StepRegs<T, VEC, NL> x, y;
         load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend, j0, cbase, x);
-        for (int jr = j0; jr < jend; jr += 4) {
-            load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend, jr + 2, cbase, y);
+        for (int jr = j0; jr < jend; jr += 2 * kStepBatch) {
+            load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend, jr + kStepBatch,
+                                   cbase, y);
             mfma_steps<T, acc_v, VEC, NL>(x, acc);
-            if (jr + 2 >= jend) break;
-            load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend, jr + 4, cbase, x);
+            if (jr + kStepBatch >= jend) break;
+            load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend,
+                                   jr + 2 * kStepBatch, cbase, x);
             mfma_steps<T, acc_v, VEC, NL>(y, acc);
         }
     }
-    // fixed-order reduction of the four partial tiles
-#pragma unroll
-    for (int t = 0; t < TILES; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[((w * TILES + t) * 4 + r) * 64 + lane] = acc[t][r];
-    __syncthreads();
+    // fixed-order reduction of the four partial tiles, in two passes over
+    // halves of the tiles so the LDS buffer stays at 16 KB
+    constexpr int PASSES = TILES >= 2 ? 2 : 1;
+    constexpr int TP = TILES / PASSES;
     T sum[TILES];
 #pragma unroll
-    for (int t = 0; t < TILES; ++t) {
-        T x = red[((0 * TILES + t) * 4 + w) * 64 + lane];
+    for (int p = 0; p < PASSES; ++p) {
+        if (p) __syncthreads();
 #pragma unroll
-        for (int v = 1; v < 4; ++v) x += red[((v * TILES + t) * 4 + w) * 64 + lane];
-        sum[t] = x;
+        for (int t = 0; t < TP; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[((w * TP + t) * 4 + r) * 64 + lane] = acc[p * TP + t][r];
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < TP; ++t) {
+            T x = red[((0 * TP + t) * 4 + w) * 64 + lane];
+#pragma unroll
+            for (int v = 1; v < 4; ++v) x += red[((v * TP + t) * 4 + w) * 64 + lane];
+            sum[p * TP + t] = x;
+        }
     }
     const int64_t row = (int64_t)rb * 16 + out_row<T>(kq, w);
     if (row >= d.m) return;
@@ -356,18 +372,24 @@ __device__ void bcsr_wg_h(const BcsrArgs& a, const DenseArgs& d, int64_t unit, f
             acc[t] = mfma32(av, bop, acc[t]);
         }
     }
-#pragma unroll
-    for (int t = 0; t < CPL; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[((w * CPL + t) * 4 + r) * 64 + lane] = acc[t][r];
-    __syncthreads();
+    constexpr int PASSES = CPL >= 2 ? 2 : 1;
+    constexpr int TP = CPL / PASSES;
     float o[CPL];
 #pragma unroll
-    for (int t = 0; t < CPL; ++t) {
-        float x = red[((0 * CPL + t) * 4 + w) * 64 + lane];
+    for (int p = 0; p < PASSES; ++p) {
+        if (p) __syncthreads();
 #pragma unroll
-        for (int v = 1; v < 4; ++v) x += red[((v * CPL + t) * 4 + w) * 64 + lane];
-        o[t] = x;
+        for (int t = 0; t < TP; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[((w * TP + t) * 4 + r) * 64 + lane] = acc[p * TP + t][r];
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < TP; ++t) {
+            float x = red[((0 * TP + t) * 4 + w) * 64 + lane];
+#pragma unroll
+            for (int v = 1; v < 4; ++v) x += red[((v * TP + t) * 4 + w) * 64 + lane];
+            o[p * TP + t] = x;
+        }
     }
     const int64_t row = (int64_t)rb * 16 + 4 * g + w;
     if (row >= d.m || !colok) return;
@@ -380,22 +402,36 @@ __device__ void bcsr_wg_h(const BcsrArgs& a, const DenseArgs& d, int64_t unit, f
 // ---------------------------------------------------------------------------
 // fused launch: workgroups [0, g_bcsr) run the BCSR-part, the rest the CSR-part
 // ---------------------------------------------------------------------------
-template <class TV, class TB, class TC, int VEC, int LPR, int BV, int BNL>
+// DO_CSR / DO_BCSR compile a part out when the plan has none of it, so a
+// one-part plan does not pay the other part's register footprint.
+template <class TV, class TB, class TC, int VEC, int LPR, int BV, int BNL, bool DO_CSR, bool DO_BCSR>
 __global__ __launch_bounds__(256) void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseArgs da, uint32_t g_bcsr,
-                                                uint32_t g_csr) {
+                                                uint32_t g_csr, int remap) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t bid = blockIdx.x;
     const int w = threadIdx.x >> 6;
     if (bid < g_bcsr) {
-        const int64_t unit = (int64_t)xcd_remap(bid, g_bcsr);
-        if constexpr (sizeof(TV) == 2) {
-            bcsr_wg_h<TV, BV>(ba, da, unit, reinterpret_cast<float*>(lds_raw));
-        } else {
-            bcsr_wg_f<TV, BV, BNL>(ba, da, unit, reinterpret_cast<TV*>(lds_raw));
+        if constexpr (DO_BCSR) {
+            // g_bcsr workgroups stride over the row-block units (one unit
+            // each unless a calibrated partition caps the part's workgroups)
+            const int64_t units = ba.n_rb * (int64_t)ba.n_panels;
+            for (int64_t unit = (int64_t)xcd_remap(bid, g_bcsr, remap); unit < units; unit += g_bcsr) {
+                if constexpr (sizeof(TV) == 2) {
+                    bcsr_wg_h<TV, BV>(ba, da, unit, reinterpret_cast<float*>(lds_raw));
+                } else {
+                    bcsr_wg_f<TV, BV, BNL>(ba, da, unit, reinterpret_cast<TV*>(lds_raw));
+                }
+                __syncthreads();  // the reduction buffer is reused by the next unit
+            }
         }
     } else {
-        const int64_t wave = (int64_t)xcd_remap(bid - g_bcsr, g_csr) * 4 + w;
-        csr_wave<TV, TB, TC, VEC, LPR, 8>(ca, da, wave);
+        if constexpr (DO_CSR) {
+            constexpr int R = 64 / LPR;
+            const int64_t waves = (ca.n_vrows + R - 1) / R;
+            for (int64_t wave = (int64_t)xcd_remap(bid - g_bcsr, g_csr, remap) * 4 + w; wave < waves;
+                 wave += (int64_t)g_csr * 4)
+                csr_wave<TV, TB, TC, VEC, LPR, 8>(ca, da, wave);
+        }
     }
 }
 
@@ -420,7 +456,7 @@ __global__ __launch_bounds__(256) void k_long_reduce(const int32_t* __restrict__
 inline uint32_t pad8(int64_t g) { return (uint32_t)(ceil_div(g, 8) * 8); }
 
 template <class TV, class TB, class TC, int VEC, int LPR, int BV, int BNL>
-int launch_cfg(const SubPlan& X, const DenseArgs& d, hipStream_t s) {
+int launch_cfg(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuery* q) {
     CsrArgs ca{X.vr_start.as<int32_t>(), X.vr_end.as<int32_t>(), X.vr_out.as<int32_t>(),
                X.csr_col.as<int32_t>(), X.csr_val.ptr, X.n_vrows};
     constexpr int PANEL = (sizeof(TV) == 2) ? 16 * BV : 16 * BV * BNL;
@@ -430,15 +466,48 @@ int launch_cfg(const SubPlan& X, const DenseArgs& d, hipStream_t s) {
     constexpr int R = 64 / LPR;
     const int64_t csr_waves = ceil_div(X.n_vrows, R);
     const int64_t bcsr_units = X.rb_bcsr * (int64_t)n_panels;
-    const uint32_t g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
-    const uint32_t g_bcsr = bcsr_units ? pad8(bcsr_units) : 0;
+    uint32_t g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
+    uint32_t g_bcsr = bcsr_units ? pad8(bcsr_units) : 0;
+    // calibrated partition (Eq. 3 analogue): caps on each part's workgroups
+    if (X.part_csr > 0 && g_csr > (uint32_t)X.part_csr) g_csr = pad8(X.part_csr);
+    if (X.part_bcsr > 0 && g_bcsr > (uint32_t)X.part_bcsr) g_bcsr = pad8(X.part_bcsr);
     if (g_csr + g_bcsr == 0) return HSPMM_OK;
     // LDS of the BCSR reduction: 4 waves x tiles x 4 registers x 64 lanes
     constexpr int TILES = (sizeof(TV) == 2) ? BV : BV * BNL;
+    constexpr int TP = TILES >= 2 ? TILES / 2 : 1;
     constexpr size_t ACC_B = (sizeof(TV) == 8) ? 8 : 4;
-    const size_t lds = g_bcsr ? (size_t)4 * TILES * 4 * 64 * ACC_B : 0;
-    hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL>), dim3(g_bcsr + g_csr), dim3(256), lds, s, ca,
-                       ba, d, g_bcsr, g_csr);
+    const size_t lds = g_bcsr ? (size_t)4 * TP * 4 * 64 * ACC_B : 0;
+    if (q) {
+        // geometry of the default launch and how many of its workgroups fit on a CU
+        q->g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
+        q->g_bcsr = bcsr_units ? pad8(bcsr_units) : 0;
+        int nb = 0;
+        hipError_t e;
+        if (q->g_bcsr && q->g_csr)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void*>(&k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, true>), 256, lds);
+        else if (q->g_csr)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void*>(&k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, false>), 256, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void*>(&k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, false, true>), 256, lds);
+        HIP_TRY(e);
+        q->wg_per_cu = nb;
+        return HSPMM_OK;
+    }
+    const dim3 grid(g_bcsr + g_csr), block(256);
+    const int rm = xcd_remap_mode();
+    if (g_bcsr && g_csr) {
+        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, true>), grid, block, lds, s, ca, ba, d,
+                           g_bcsr, g_csr, rm);
+    } else if (g_csr) {
+        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, false>), grid, block, 0, s, ca, ba, d,
+                           g_bcsr, g_csr, rm);
+    } else {
+        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, false, true>), grid, block, lds, s, ca, ba, d,
+                           g_bcsr, g_csr, rm);
+    }
     HIP_LAUNCH_CHECK();
     if (X.n_long > 0) {
         typedef typename Elem<TB>::acc_t acc_t;
@@ -471,53 +540,61 @@ inline int lpr_for(int64_t n, int vec) {
     }
 
 template <class TV, class TB, class TC>
-int dispatch_dtype(const SubPlan& X, const DenseArgs& d, bool vec_ok, hipStream_t s);
+int dispatch_dtype(const SubPlan& X, const DenseArgs& d, bool vec_ok, hipStream_t s, LaunchQuery* q);
 
 // FP32: VEC 4 (16-byte loads) when n, ld and pointers allow, else scalar
 template <>
-int dispatch_dtype<float, float, float>(const SubPlan& X, const DenseArgs& d, bool vec_ok, hipStream_t s) {
+int dispatch_dtype<float, float, float>(const SubPlan& X, const DenseArgs& d, bool vec_ok, hipStream_t s,
+                                        LaunchQuery* q) {
     if (vec_ok) {
         const int lpr = lpr_for(d.n, 4);
+#ifndef HSPMM_F32_NL
+#define HSPMM_F32_NL 2
+#endif
         if (d.n <= 64) {
-            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<float, float, float, 4, LPR, 4, 1>(X, d, s)));
+            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<float, float, float, 4, LPR, 4, 1>(X, d, s, q)));
         } else {
-            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<float, float, float, 4, LPR, 4, 2>(X, d, s)));
+            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<float, float, float, 4, LPR, 4, HSPMM_F32_NL>(X, d, s, q)));
         }
     }
-    return launch_cfg<float, float, float, 1, 64, 1, 4>(X, d, s);
+    return launch_cfg<float, float, float, 1, 64, 1, 4>(X, d, s, q);
 }
 
 template <>
-int dispatch_dtype<double, double, double>(const SubPlan& X, const DenseArgs& d, bool vec_ok, hipStream_t s) {
+int dispatch_dtype<double, double, double>(const SubPlan& X, const DenseArgs& d, bool vec_ok, hipStream_t s,
+                                           LaunchQuery* q) {
     if (vec_ok) {
         const int lpr = lpr_for(d.n, 2);
         if (d.n <= 32) {
-            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<double, double, double, 2, LPR, 2, 1>(X, d, s)));
+            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<double, double, double, 2, LPR, 2, 1>(X, d, s, q)));
         } else {
-            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<double, double, double, 2, LPR, 2, 2>(X, d, s)));
+            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<double, double, double, 2, LPR, 2, 2>(X, d, s, q)));
         }
     }
-    return launch_cfg<double, double, double, 1, 64, 1, 4>(X, d, s);
+    return launch_cfg<double, double, double, 1, 64, 1, 4>(X, d, s, q);
 }
 
 template <class TH>
-int dispatch_half(const SubPlan& X, const DenseArgs& d, bool vec_ok, hipStream_t s) {
+int dispatch_half(const SubPlan& X, const DenseArgs& d, bool vec_ok, hipStream_t s, LaunchQuery* q) {
     if (vec_ok) {
         const int lpr = lpr_for(d.n, 8);
         if (d.n <= 64) {
-            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<TH, TH, float, 8, LPR, 4, 1>(X, d, s)));
+            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<TH, TH, float, 8, LPR, 4, 1>(X, d, s, q)));
         } else {
-            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<TH, TH, float, 8, LPR, 8, 1>(X, d, s)));
+            HSPMM_LPR_SWITCH(lpr, return (launch_cfg<TH, TH, float, 8, LPR, 8, 1>(X, d, s, q)));
         }
     }
-    return launch_cfg<TH, TH, float, 1, 64, 1, 1>(X, d, s);
+    return launch_cfg<TH, TH, float, 1, 64, 1, 1>(X, d, s, q);
 }
 
 }  // namespace
 
 int launch_forward(Plan& p, SubPlan& X, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc,
-                   hipStream_t s) {
-    if (X.m == 0 || n == 0) return HSPMM_OK;
+                   hipStream_t s, LaunchQuery* q) {
+    if (X.m == 0 || n == 0) {
+        if (q) *q = LaunchQuery{};
+        return HSPMM_OK;
+    }
     const size_t eb = dtype_size(X.ct);
     const size_t ec = dtype_size(out_dtype(X.ct));
     // partial rows of split CSR rows
@@ -532,10 +609,10 @@ int launch_forward(Plan& p, SubPlan& X, int64_t n, const void* B, int64_t ldb, v
     const bool vec_ok = (n % vec_elems == 0) && (ldb % vec_elems == 0) && (ldc % vec_elems == 0) &&
                         aligned(B, 16) && aligned(C, 16) && (ec * vec_elems) % 16 == 0;
     switch (X.ct) {
-        case HSPMM_F32: return dispatch_dtype<float, float, float>(X, d, vec_ok, s);
-        case HSPMM_F64: return dispatch_dtype<double, double, double>(X, d, vec_ok, s);
-        case HSPMM_F16: return dispatch_half<half_t>(X, d, vec_ok, s);
-        case HSPMM_BF16: return dispatch_half<bf16_t>(X, d, vec_ok, s);
+        case HSPMM_F32: return dispatch_dtype<float, float, float>(X, d, vec_ok, s, q);
+        case HSPMM_F64: return dispatch_dtype<double, double, double>(X, d, vec_ok, s, q);
+        case HSPMM_F16: return dispatch_half<half_t>(X, d, vec_ok, s, q);
+        case HSPMM_BF16: return dispatch_half<bf16_t>(X, d, vec_ok, s, q);
         default: return fail(HSPMM_ERR_DTYPE, "unsupported compute dtype");
     }
 }

@@ -65,9 +65,10 @@ def test_struct_sizes_match_header():
     from paper_2511_08158_amd import _lib
     src = (
         '#include <stdio.h>\n#include <stddef.h>\n#include "hspmm.h"\n'
-        'int main(){printf("%zu %zu %zu %zu %zu\\n", sizeof(hspmm_plan_opts), sizeof(hspmm_plan_info),'
+        'int main(){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(hspmm_plan_opts), sizeof(hspmm_plan_info),'
         ' offsetof(hspmm_plan_opts, max_workspace_bytes), offsetof(hspmm_plan_info, plan_ms),'
-        ' offsetof(hspmm_plan_info, t_nblk)); return 0;}\n')
+        ' offsetof(hspmm_plan_info, t_nblk), sizeof(hspmm_calib_info), offsetof(hspmm_calib_info, applied));'
+        ' return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         c = Path(d) / "t.c"
         c.write_text(src)
@@ -76,4 +77,4 @@ def test_struct_sizes_match_header():
         got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert got == [ctypes.sizeof(_lib.PlanOpts), ctypes.sizeof(_lib.PlanInfo),
                    _lib.PlanOpts.max_workspace_bytes.offset, _lib.PlanInfo.plan_ms.offset,
-                   _lib.PlanInfo.t_nblk.offset]
+                   _lib.PlanInfo.t_nblk.offset, ctypes.sizeof(_lib.CalibInfo), _lib.CalibInfo.applied.offset]
