@@ -42,7 +42,83 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (calibrates HBM byte counters)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="structure sweep: forward GFLOP/s of the AUTO split vs CSR-only per matrix and N")
+    ap.add_argument("--sweep-rows", type=int, default=100_000, help="row cap of the sweep matrices")
+    ap.add_argument("--sweep-n", default="16,32,64,128,256")
     return ap.parse_args()
+
+
+def sweep(args):
+    """Forward throughput of AUTO vs CSR-only over the 64 seeded matrices of
+    the structure sweep (uniform / banded / block-diagonal / power law),
+    FP32, one JSON line per (matrix, N) and a summary line.  The BCSR-only
+    plan is timed too, so AUTO is also compared with the better fixed split."""
+    import numpy as np
+    import torch
+
+    import gen
+    import oracle
+    import paper_2511_08158_amd as hs
+
+    dev = torch.device("cuda:0")
+    ns = [int(x) for x in args.sweep_n.split(",")]
+    wins, ratios, rows, best_ratios = 0, [], [], []
+    for i in range(64):
+        a = gen.config5(i, max_rows=args.sweep_rows)
+        spec = a.meta
+        vals = torch.tensor(a.vals, device=dev)
+        for n in ns:
+            b = gen.dense(i, gen.DENSE, a.k, n, "uniform")
+            B = torch.tensor(b, device=dev, dtype=torch.float32)
+            res = {}
+            for split in ("auto", "csr", "bcsr"):
+                p = hs.Plan(a.row_ptr, a.col_idx, vals, (a.m, a.k), compute=torch.float32, split=split, n_hint=n)
+                C = p.run(B)
+                for _ in range(3):
+                    p.run(B, out=C)
+                reps = 20
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    p.run(B, out=C)
+                e1.record()
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) / reps * 1e-3
+                info = p.info()
+                res[split] = {"t": t, "gflops": 2.0 * a.nnz * n / t / 1e9, "rb_bcsr": info["rb_bcsr"],
+                              "rows_csr": info["rows_csr"], "fill": info["fill"]}
+                if split == "auto" and n == ns[0]:
+                    # sampled rows against the oracle
+                    g = np.random.default_rng(i)
+                    rs = np.sort(g.choice(a.m, min(a.m, 256), replace=False))
+                    lens = np.diff(a.row_ptr)[rs]
+                    rp = np.concatenate([[0], np.cumsum(lens)])
+                    col = np.concatenate([a.col_idx[a.row_ptr[r]:a.row_ptr[r + 1]] for r in rs])
+                    val = np.concatenate([a.vals[a.row_ptr[r]:a.row_ptr[r + 1]] for r in rs])
+                    ref = oracle.spmm(rs.size, a.k, rp, col, val, b)
+                    err = oracle.rel_err(C[torch.as_tensor(rs, device=dev)].double().cpu().numpy(), ref)
+                    res["err"] = err
+                p.close()
+            sp = res["csr"]["t"] / res["auto"]["t"]
+            ratios.append(sp)
+            best_ratios.append(min(res["csr"]["t"], res["bcsr"]["t"]) / res["auto"]["t"])
+            wins += sp >= 0.98
+            line = {"i": i, "class": spec["class"], "m": a.m, "nnz": a.nnz, "n": n,
+                    "auto_gflops": round(res["auto"]["gflops"], 1), "csr_gflops": round(res["csr"]["gflops"], 1),
+                    "bcsr_gflops": round(res["bcsr"]["gflops"], 1), "speedup": round(sp, 3), "rb_bcsr": res["auto"]["rb_bcsr"],
+                    "rb_total": (a.m + 15) // 16, "fill": round(res["auto"]["fill"], 3)}
+            if "err" in res:
+                line["err"] = float(f"{res['err']:.2e}")
+            rows.append(line)
+            print(json.dumps(line), flush=True)
+    gm = float(np.exp(np.mean(np.log(ratios))))
+    print(json.dumps({"sweep_summary": {"runs": len(ratios), "auto_not_slower_share": round(wins / len(ratios), 3),
+                                        "geomean_speedup_auto_vs_csr": round(gm, 3),
+                                        "max_speedup": round(max(ratios), 3), "min_speedup": round(min(ratios), 3),
+                                        "geomean_auto_vs_best_fixed": round(float(np.exp(np.mean(np.log(best_ratios)))), 3),
+                                        "min_auto_vs_best_fixed": round(min(best_ratios), 3),
+                                        "max_err": max(r.get("err", 0.0) for r in rows)}}), flush=True)
 
 
 def copy_probe():
@@ -90,6 +166,9 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.sweep:
+        sweep(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "

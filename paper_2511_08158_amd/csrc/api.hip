@@ -70,6 +70,31 @@ int xcd_remap_mode() {
     return mode;
 }
 
+int bcsr_persistent() {
+    static const int mode = [] {
+        const char* e = getenv("HSPMM_BCSR_PERSIST");
+        return (e && e[0] == '1') ? 1 : 0;
+    }();
+    return mode;
+}
+
+int bwd_concurrent() {
+    // read on every backward call, so a process can switch it between calls
+    const char* e = getenv("HSPMM_BWD_CONCURRENT");
+    return (e && e[0] == '1') ? 1 : 0;
+}
+
+int hybrid_launch_mode() {
+    const char* e = getenv("HSPMM_HYBRID_LAUNCH");
+    return (e && e[0] == '2') ? 2 : 1;
+}
+
+Plan::~Plan() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
+}
+
 int ensure_ws(Plan& p, size_t bytes) {
     if (bytes <= p.ws.bytes) return HSPMM_OK;
     HIP_TRY(hipDeviceSynchronize());
@@ -168,19 +193,38 @@ int hybrid_spmm_backward(hspmm_plan_t h, int64_t n, const void* B, int64_t ldb, 
     Plan& p = h->p;
     if (n < 0) return fail(HSPMM_ERR_ARG, "n < 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool do_dB = dB && n > 0 && p.k > 0;
+    const bool do_dA = dA_vals && p.nnz_in > 0;
     if (dB) {
         if (!p.has_T) return fail(HSPMM_ERR_NO_BACKWARD, "plan was built without want_backward");
-        if (n > 0 && p.k > 0) {
+        if (do_dB) {
             if (lddb < n || (p.m > 0 && lddc < n)) return fail(HSPMM_ERR_ARG, "leading dimension smaller than n");
             if (p.m > 0 && !dC) return fail(HSPMM_ERR_ARG, "dC is NULL");
-            HSPMM_TRY(launch_forward(p, p.T, n, dC, lddc, dB, lddb, s));
         }
     }
-    if (dA_vals && p.nnz_in > 0) {
+    if (do_dA) {
         if (n > 0 && (!B || !dC)) return fail(HSPMM_ERR_ARG, "B or dC is NULL");
         if (n > 0 && (ldb < n || lddc < n)) return fail(HSPMM_ERR_ARG, "leading dimension smaller than n");
-        HSPMM_TRY(launch_sddmm(p, n, B, ldb, dC, lddc, dA_vals, s));
     }
+    if (do_dB && do_dA && bwd_concurrent()) {
+        // the two gradients are independent: SDDMM on the side stream,
+        // forked from and joined back into the caller's stream
+        if (!p.side) {
+            HIP_TRY(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventRecord(p.ev_fork, s));
+        HIP_TRY(hipStreamWaitEvent(p.side, p.ev_fork, 0));
+        const int rc = launch_sddmm(p, n, B, ldb, dC, lddc, dA_vals, p.side, &p.ws2);
+        HIP_TRY(hipEventRecord(p.ev_join, p.side));
+        HSPMM_TRY(rc);
+        const int rc2 = launch_forward(p, p.T, n, dC, lddc, dB, lddb, s);
+        HIP_TRY(hipStreamWaitEvent(s, p.ev_join, 0));
+        return rc2;
+    }
+    if (do_dB) HSPMM_TRY(launch_forward(p, p.T, n, dC, lddc, dB, lddb, s));
+    if (do_dA) HSPMM_TRY(launch_sddmm(p, n, B, ldb, dC, lddc, dA_vals, s, nullptr));
     return HSPMM_OK;
 }
 

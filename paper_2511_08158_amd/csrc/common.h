@@ -195,6 +195,19 @@ __device__ inline uint32_t xcd_remap(uint32_t id, uint32_t G, int mode) {
     return (id & 7u) * per + (id >> 3);
 }
 int xcd_remap_mode();
+// 0 (default): one workgroup per row block of the BCSR-part; 1
+// (HSPMM_BCSR_PERSIST=1): resident workgroups that each take a contiguous
+// range of row blocks, prefetching the next one's metadata (measured
+// slower on the block stencil, kept as a tuning knob).
+int bcsr_persistent();
+// 0 (default): the backward runs dB then dA on the caller's stream; 1
+// (HSPMM_BWD_CONCURRENT=1): dA = SDDMM on a plan-owned side stream beside dB
+// (each kernel fills the GPU on large matrices, and the fork/join cost more
+// than the overlap gained on the block stencil; kept as a tuning knob).
+int bwd_concurrent();
+// launch of a plan with both parts: 1 one fused kernel, 2 one kernel per
+// part (HSPMM_HYBRID_LAUNCH; read on every call)
+int hybrid_launch_mode();
 
 constexpr int kNumXcd = 8;
 

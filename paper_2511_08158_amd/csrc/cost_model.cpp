@@ -1,6 +1,7 @@
 // Host cost model (pure host arithmetic, no device calls).
 #include "cost_model.h"
 
+#include <algorithm>
 #include <cmath>
 #include <limits>
 
@@ -8,19 +9,12 @@ namespace hspmm {
 
 RowBlockCost rowblock_cost(const MachineModel& mm, int64_t nnz, int64_t nblk, int64_t n, int sv, int sb,
                            int br, int kc) {
+    (void)sv;
+    (void)br;
     RowBlockCost c;
-    // CSR-part: per entry a column index and a value are streamed, and one
-    // row segment of B (n elements) is gathered.
-    const double csr_stream = (double)nnz * (sv + 4);
-    const double csr_gather = (double)nnz * n * sb;
-    c.t_csr = csr_stream / mm.bw_stream + csr_gather / mm.bw_gather + nnz * mm.t_entry_csr;
-    // BCSR-part: per tile br padded values and one column index are streamed
-    // (tiles padded up to the MFMA depth kc), and one row of B is gathered
-    // per non-empty tile; the gathered row then serves all br rows.
+    c.t_csr = (double)nnz * (mm.t_entry + (double)n * sb / mm.bw_csr);
     const int64_t padded = nblk == 0 ? 0 : ((nblk + kc - 1) / kc) * kc;
-    const double b_stream = (double)padded * (br * sv + 4);
-    const double b_gather = (double)nblk * n * sb;
-    c.t_bcsr = b_stream / mm.bw_stream + b_gather / mm.bw_gather + nblk * mm.t_blk_bcsr;
+    c.t_bcsr = (double)padded * std::max(mm.t_blk, (double)n * sb / mm.bw_bcsr);
     return c;
 }
 

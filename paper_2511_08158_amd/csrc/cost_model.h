@@ -7,14 +7,20 @@
 
 namespace hspmm {
 
-// Machine constants of one MI355X used by the byte/time model.  The
-// bandwidths are effective figures (achievable HBM streaming, and the rate
-// at which gathered rows of B arrive through L2/MALL), not peaks.
+// Machine constants of one MI355X used by the time model.  The rates are
+// effective figures of this library's two kernels, fitted to the forward
+// times of the CSR-only and BCSR-only plans of the 64-matrix structure sweep
+// (FP32, n = 16..256, relative least squares):
+//   CSR-part  = nnz * (t_entry + n s_b / bw_csr)       (one gathered B row
+//               segment per entry, through L2/MALL);
+//   BCSR-part = padded tiles * max(t_blk, n s_b / bw_bcsr)   (a tile costs
+//               its MFMA step, value and index loads until its gathered
+//               B row segment takes longer).
 struct MachineModel {
-    double bw_stream = 5.0e12;   // B/s for streamed A-part arrays
-    double bw_gather = 12.0e12;  // B/s for gathered B rows (cache hits dominate)
-    double t_entry_csr = 0.0;    // extra s per CSR entry per wave (issue cost)
-    double t_blk_bcsr = 0.0;     // extra s per tile
+    double bw_csr = 20.0e12;
+    double bw_bcsr = 6.5e12;
+    double t_entry = 0.0;
+    double t_blk = 31.0e-12;
     int cus = 256;
 };
 
@@ -25,7 +31,9 @@ struct RowBlockCost {
 
 // Predicted time of one row block with `nnz` entries spread over `nblk`
 // non-empty tiles, for dense width n, value bytes sv, dense bytes sb, and
-// the MFMA K depth kc (tiles are padded to a multiple of kc).
+// the MFMA K depth kc (tiles are padded to a multiple of kc).  Each CSR
+// entry gathers one B row segment; each BCSR tile gathers one and serves
+// all br rows with it.
 RowBlockCost rowblock_cost(const MachineModel& mm, int64_t nnz, int64_t nblk, int64_t n, int sv, int sb,
                            int br, int kc);
 

@@ -64,7 +64,15 @@ struct Plan {
     bool has_T = false;
 
     DevBuf ws;            // run/backward scratch
+    DevBuf ws2;           // scratch of the SDDMM when it runs beside dB
     double plan_ms = 0.0;
+
+    // side stream of the backward: dA = SDDMM runs on it concurrently with
+    // dB = A^T dC, forked from and joined back to the caller's stream by
+    // events (default stream priority)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    ~Plan();
 };
 
 // vals/row_of helpers shared by the plan build and update_values
@@ -81,7 +89,7 @@ int launch_forward(Plan& p, SubPlan& X, int64_t n, const void* B, int64_t ldb, v
                    hipStream_t s, LaunchQuery* q = nullptr);
 // SDDMM on A's pattern: dA_canon[c] (or dA_in[e] via canon_of_orig)
 int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dA,
-                 hipStream_t s);
+                 hipStream_t s, DevBuf* ws);
 int ensure_ws(Plan& p, size_t bytes);
 
 int calibrate(Plan& p, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc, int reps,

@@ -469,8 +469,17 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
     X.rows_csr = (int64_t)rows.size();
     X.nnz_csr = acc;
     // virtual rows: rows longer than `seg` entries are cut into segments whose
-    // partial rows are summed in order by a second kernel
-    const int32_t seg = X.seg > 0 ? X.seg : 256;
+    // partial rows are summed in order by a second kernel.  A lane group walks
+    // its segment in dependent rounds of gathers, so a long segment is a long
+    // critical path when the CSR-part has too little work to hide it: the
+    // segment length shrinks (256 down to 32) until the CSR-part holds about
+    // kSegTarget segments' worth of entries.
+    constexpr int64_t kSegTarget = 16384;
+    int32_t seg = X.seg;
+    if (seg <= 0) {
+        seg = 256;
+        while (seg > 32 && X.nnz_csr < (int64_t)seg * kSegTarget) seg >>= 1;
+    }
     X.seg = seg;
     std::vector<int32_t> vs, ve, vo, vrow, lrow, lfirst, lcnt;
     int64_t nparts = 0;

@@ -160,9 +160,11 @@ template <> __device__ inline int out_row<double>(int g, int r) { return g + 4 *
 // One workgroup per row block.  K of the MFMA runs over the n columns:
 // lane (i, q) supplies columns kbase + q*VEC + v of dC row i and of B row j,
 // so each of the VEC MFMAs of a step consumes one component.  When n fits in
-// NKR steps the 16 x n slab of dC is staged once in LDS and held in
-// registers by all four waves; the row block's chunks of 16 tiles are dealt
-// to the waves round-robin (independent outputs, no reduction needed).
+// NKR steps the 16 x n slab of dC is staged once in LDS and read from there
+// by all four waves at each step (holding it in registers instead costs
+// NKR*VEC registers and with them occupancy); the row block's chunks of 16
+// tiles are dealt to the waves round-robin (independent outputs, no
+// reduction needed).
 template <class TB, class TG, int VEC, int NKR>
 __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
     typedef typename AccOf<TG>::type acc_v;
@@ -181,7 +183,6 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
     const bool arow_ok = arow < a.m;
     const int nsteps = (int)ceil_div(a.n, STEP);
     const bool cached = nsteps <= NKR;
-    TG gc[NKR][VEC];
     if (cached) {
         for (int idx = threadIdx.x; idx < 16 * NMAX; idx += 256) {
             const int i = idx / NMAX, c = idx - i * NMAX;
@@ -189,11 +190,17 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
             lds[i * LDR + c] = (row < a.m && c < a.n) ? dC[row * a.lddc + c] : TG(0);
         }
         __syncthreads();
-#pragma unroll
-        for (int s = 0; s < NKR; ++s)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) gc[s][v] = lds[j * LDR + s * STEP + q * VEC + v];
     }
+    const TG* __restrict__ gl_row = lds + j * LDR + q * VEC;
+#ifndef HSPMM_SDD_GATHER
+#define HSPMM_SDD_GATHER 4
+#endif
+    // steps whose gathers are in flight together: 4 (a lane's 4 x 16-byte
+    // gathers) measured faster than all NKR at once (FP32 -9%, FP16 -17%,
+    // FP64 -9% on the block stencil), the smaller register set buying
+    // occupancy, and no slower than 2
+    constexpr int GB = (HSPMM_SDD_GATHER > 0 && HSPMM_SDD_GATHER < NKR) ? HSPMM_SDD_GATHER : NKR;
+    static_assert(NKR % GB == 0, "gather batch must divide the cached steps");
     for (int it0 = 0; 16 * w + 64 * it0 < cnt; it0 += 4) {
         // tile columns of this wave's next four chunks: lane l -> chunk it0 + l/16
         const int pre = 16 * w + 64 * (it0 + (lane >> 4)) + j;
@@ -214,23 +221,31 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
             }
             acc_v acc = acc_v{0, 0, 0, 0};
             if (cached) {
-                // all gathers of the chunk first, then the products
-                TG bv[NKR][VEC];
+                // the gathers of GB steps first, then their products
 #pragma unroll
-                for (int s = 0; s < NKR; ++s) {
-                    const int64_t c = (int64_t)s * STEP + q * VEC;
-                    if (s < nsteps && bok && c < a.n) {
-                        load_as<TB, VEC>(B + (int64_t)bc * a.ldb + c, bv[s]);
-                    } else {
+                for (int s0 = 0; s0 < NKR; s0 += GB) {
+                    TG bv[GB][VEC];
 #pragma unroll
-                        for (int v = 0; v < VEC; ++v) bv[s][v] = TG(0);
+                    for (int t = 0; t < GB; ++t) {
+                        const int s = s0 + t;
+                        const int64_t c = (int64_t)s * STEP + q * VEC;
+                        if (s < nsteps && bok && c < a.n) {
+                            load_as<TB, VEC>(B + (int64_t)bc * a.ldb + c, bv[t]);
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < VEC; ++v) bv[t][v] = TG(0);
+                        }
                     }
+#pragma unroll
+                    for (int t = 0; t < GB; ++t)
+                        if (s0 + t < nsteps) {
+                            TG gv[VEC];
+#pragma unroll
+                            for (int v = 0; v < VEC; ++v) gv[v] = gl_row[(s0 + t) * STEP + v];
+#pragma unroll
+                            for (int v = 0; v < VEC; ++v) acc = mfma4(gv[v], bv[t][v], acc);
+                        }
                 }
-#pragma unroll
-                for (int s = 0; s < NKR; ++s)
-                    if (s < nsteps)
-#pragma unroll
-                        for (int v = 0; v < VEC; ++v) acc = mfma4(gc[s][v], bv[s][v], acc);
             } else {
                 for (int s = 0; s < nsteps; ++s) {
                     const int64_t c = (int64_t)s * STEP + q * VEC;
@@ -302,7 +317,13 @@ int launch_sdd(const SubPlan& X, SddArgs a, hipStream_t s) {
     const size_t lds = g_bcsr ? (size_t)16 * (NKR * 4 * BVEC + 4) * sizeof(TG) : 0;
     const dim3 grid(g_bcsr + g_csr), block(256);
     const int rm = xcd_remap_mode();
-    if (g_bcsr && g_csr) {
+    if (g_bcsr && g_csr && hybrid_launch_mode() == 2) {
+        hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, false, true>), dim3(g_bcsr), block, lds, s, a, g_bcsr,
+                           0u, rm);
+        HIP_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, true, false>), dim3(g_csr), block, 0, s, a, 0u, g_csr,
+                           rm);
+    } else if (g_bcsr && g_csr) {
         hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, true, true>), grid, block, lds, s, a, g_bcsr, g_csr,
                            rm);
     } else if (g_csr) {
@@ -330,14 +351,18 @@ inline bool aligned(const void* p, size_t al) { return ((uintptr_t)p % al) == 0;
 }  // namespace
 
 int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dA,
-                 hipStream_t s) {
+                 hipStream_t s, DevBuf* wsb) {
     SubPlan& X = p.A;
     if (p.nnz == 0) return HSPMM_OK;
     const size_t go = p.compute == HSPMM_F64 ? 8 : 4;
     void* target = dA;
+    DevBuf& ws = wsb ? *wsb : p.ws;
     if (!p.canonical) {
-        HSPMM_TRY(ensure_ws(p, (size_t)p.nnz * go));
-        target = p.ws.ptr;
+        if (ws.bytes < (size_t)p.nnz * go) {
+            HIP_TRY(hipDeviceSynchronize());
+            HSPMM_TRY(p.al.alloc(ws, (size_t)p.nnz * go));
+        }
+        target = ws.ptr;
     }
     if (n == 0) {
         HIP_TRY(hipMemsetAsync(target, 0, (size_t)p.nnz * go, s));
@@ -379,10 +404,10 @@ int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC,
     if (!p.canonical) {
         const unsigned g = (unsigned)std::min<int64_t>(ceil_div(p.nnz_in, 256), 65536);
         if (go == 8) {
-            hipLaunchKernelGGL(k_gather_dA<double>, dim3(g), dim3(256), 0, s, p.ws.as<double>(),
+            hipLaunchKernelGGL(k_gather_dA<double>, dim3(g), dim3(256), 0, s, ws.as<double>(),
                                p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<double*>(dA));
         } else {
-            hipLaunchKernelGGL(k_gather_dA<float>, dim3(g), dim3(256), 0, s, p.ws.as<float>(),
+            hipLaunchKernelGGL(k_gather_dA<float>, dim3(g), dim3(256), 0, s, ws.as<float>(),
                                p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<float*>(dA));
         }
         HIP_LAUNCH_CHECK();

@@ -240,19 +240,41 @@ __device__ inline void mfma_steps(const StepRegs<T, VEC, NL>& o, ACC (&acc)[VEC 
 // to 16 rounds are fetched with one coalesced load and handed to the lanes
 // by a shuffle, so B loads never wait on an index load, and the loads of the
 // next kStepBatch steps are in flight while the MFMAs of the current ones run.
+// Per-unit metadata of the BCSR-part (row block, tile range, the tile
+// columns of the first 16 rounds).  Loading it is a short chain of
+// dependent loads, so the workgroup fetches the next unit's metadata
+// before it works on the current one.
+struct UnitMeta {
+    int rb, b0, cnt, panel, colreg;
+    bool valid;
+};
+
+__device__ inline UnitMeta bcsr_meta(const BcsrArgs& a, int64_t unit) {
+    UnitMeta m{0, 0, 0, 0, 0, false};
+    const int64_t slot = unit / a.n_panels;
+    if (slot >= a.n_rb) return m;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    m.valid = true;
+    m.panel = (int)(unit - slot * a.n_panels);
+    m.rb = a.rb[slot];
+    m.b0 = a.blk_ptr[slot];
+    m.cnt = a.blk_cnt[slot];
+    const int pre = 16 * (lane >> 2) + 4 * w + (lane & 3);
+    m.colreg = pre < m.cnt ? a.blk_col[m.b0 + pre] : 0;
+    return m;
+}
+
 template <class T, int VEC, int NL>
-__device__ void bcsr_wg_f(const BcsrArgs& a, const DenseArgs& d, int64_t unit, T* red) {
+__device__ void bcsr_wg_f(const BcsrArgs& a, const DenseArgs& d, const UnitMeta& um, T* red) {
     typedef typename AccOf<T>::type acc_v;
     constexpr int PANEL = 16 * VEC * NL;
     constexpr int TILES = VEC * NL;
-    const int64_t slot = unit / a.n_panels;
-    if (slot >= a.n_rb) return;  // uniform over the workgroup
-    const int panel = (int)(unit - slot * a.n_panels);
+    if (!um.valid) return;  // uniform over the workgroup
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane & 15, kq = lane >> 4;
-    const int rb = a.rb[slot];
-    const int b0 = a.blk_ptr[slot];
-    const int cnt = a.blk_cnt[slot];
-    const int64_t cbase = (int64_t)panel * PANEL + (int64_t)j * VEC;
+    const int rb = um.rb;
+    const int b0 = um.b0;
+    const int cnt = um.cnt;
+    const int64_t cbase = (int64_t)um.panel * PANEL + (int64_t)j * VEC;
     const T* __restrict__ vals = static_cast<const T*>(a.val);
     const T* __restrict__ B = static_cast<const T*>(d.B);
     acc_v acc[TILES];
@@ -261,8 +283,11 @@ __device__ void bcsr_wg_f(const BcsrArgs& a, const DenseArgs& d, int64_t unit, T
 
     const int nrounds = (cnt + 15) >> 4;  // a round = 16 tiles = one step per wave
     for (int j0 = 0; j0 < nrounds; j0 += 16) {
-        const int pre = 16 * (j0 + (lane >> 2)) + 4 * w + (lane & 3);
-        const int colreg = pre < cnt ? a.blk_col[b0 + pre] : 0;
+        int colreg = um.colreg;
+        if (j0 > 0) {
+            const int pre = 16 * (j0 + (lane >> 2)) + 4 * w + (lane & 3);
+            colreg = pre < cnt ? a.blk_col[b0 + pre] : 0;
+        }
         const int jend = min(nrounds, j0 + 16);
         StepRegs<T, VEC, NL> x, y;
         load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend, j0, cbase, x);
@@ -403,10 +428,27 @@ __device__ void bcsr_wg_h(const BcsrArgs& a, const DenseArgs& d, int64_t unit, f
 // fused launch: workgroups [0, g_bcsr) run the BCSR-part, the rest the CSR-part
 // ---------------------------------------------------------------------------
 // DO_CSR / DO_BCSR compile a part out when the plan has none of it, so a
-// one-part plan does not pay the other part's register footprint.
+// one-part plan does not pay the other part's register footprint.  When both
+// parts are compiled in, the CSR lane groups keep fewer gathers in flight
+// (4 instead of 8) and the kernel is held to the waves per SIMD that the
+// BCSR-only kernel reaches: the BCSR-part is latency-bound and loses in
+// proportion to lost occupancy, while the CSR-part's lost depth per wave is
+// made up by the extra waves.
+template <class TV, int VEC, int BV, int BNL>
+constexpr int bcsr_waves_per_simd() {
+    // register-limited occupancy of the BCSR-only instantiations on gfx950
+    // (VGPR + AGPR count from the compiler's resource usage report); FP16 /
+    // BF16 with 4 column groups is held one wave lower, where the fused
+    // kernel fits without spilling
+    if (sizeof(TV) == 2) return VEC == 1 ? 8 : (BV == 8 ? 4 : 5);
+    if (sizeof(TV) == 8) return (VEC == 1 || BNL >= 2) ? 4 : 7;
+    return VEC == 1 ? 7 : (BNL >= 2 ? 5 : 8);
+}
+
 template <class TV, class TB, class TC, int VEC, int LPR, int BV, int BNL, bool DO_CSR, bool DO_BCSR>
-__global__ __launch_bounds__(256) void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseArgs da, uint32_t g_bcsr,
-                                                uint32_t g_csr, int remap) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(DO_CSR && DO_BCSR ? bcsr_waves_per_simd<TV, VEC, BV, BNL>() : 1)))
+void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseArgs da, uint32_t g_bcsr, uint32_t g_csr, int remap) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t bid = blockIdx.x;
     const int w = threadIdx.x >> 6;
@@ -415,13 +457,24 @@ __global__ __launch_bounds__(256) void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseAr
             // g_bcsr workgroups stride over the row-block units (one unit
             // each unless a calibrated partition caps the part's workgroups)
             const int64_t units = ba.n_rb * (int64_t)ba.n_panels;
-            for (int64_t unit = (int64_t)xcd_remap(bid, g_bcsr, remap); unit < units; unit += g_bcsr) {
-                if constexpr (sizeof(TV) == 2) {
+            if constexpr (sizeof(TV) == 2) {
+                for (int64_t unit = (int64_t)xcd_remap(bid, g_bcsr, remap); unit < units; unit += g_bcsr) {
                     bcsr_wg_h<TV, BV>(ba, da, unit, reinterpret_cast<float*>(lds_raw));
-                } else {
-                    bcsr_wg_f<TV, BV, BNL>(ba, da, unit, reinterpret_cast<TV*>(lds_raw));
+                    __syncthreads();  // the reduction buffer is reused by the next unit
                 }
-                __syncthreads();  // the reduction buffer is reused by the next unit
+            } else {
+                // a contiguous range of units per workgroup (neighbouring row
+                // blocks share gathered rows of B in the XCD's L2)
+                const int64_t per = (units + g_bcsr - 1) / g_bcsr;
+                int64_t unit = (int64_t)xcd_remap(bid, g_bcsr, remap) * per;
+                const int64_t uend = unit + per < units ? unit + per : units;
+                UnitMeta cur = unit < uend ? bcsr_meta(ba, unit) : UnitMeta{0, 0, 0, 0, 0, false};
+                for (; unit < uend; ++unit) {
+                    const UnitMeta nxt = unit + 1 < uend ? bcsr_meta(ba, unit + 1) : UnitMeta{0, 0, 0, 0, 0, false};
+                    bcsr_wg_f<TV, BV, BNL>(ba, da, cur, reinterpret_cast<TV*>(lds_raw));
+                    __syncthreads();  // the reduction buffer is reused by the next unit
+                    cur = nxt;
+                }
             }
         }
     } else {
@@ -430,7 +483,7 @@ __global__ __launch_bounds__(256) void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseAr
             const int64_t waves = (ca.n_vrows + R - 1) / R;
             for (int64_t wave = (int64_t)xcd_remap(bid - g_bcsr, g_csr, remap) * 4 + w; wave < waves;
                  wave += (int64_t)g_csr * 4)
-                csr_wave<TV, TB, TC, VEC, LPR, 8>(ca, da, wave);
+                csr_wave<TV, TB, TC, VEC, LPR, (DO_BCSR ? 4 : 8)>(ca, da, wave);
         }
     }
 }
@@ -468,15 +521,32 @@ int launch_cfg(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuery*
     const int64_t bcsr_units = X.rb_bcsr * (int64_t)n_panels;
     uint32_t g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
     uint32_t g_bcsr = bcsr_units ? pad8(bcsr_units) : 0;
-    // calibrated partition (Eq. 3 analogue): caps on each part's workgroups
-    if (X.part_csr > 0 && g_csr > (uint32_t)X.part_csr) g_csr = pad8(X.part_csr);
-    if (X.part_bcsr > 0 && g_bcsr > (uint32_t)X.part_bcsr) g_bcsr = pad8(X.part_bcsr);
     if (g_csr + g_bcsr == 0) return HSPMM_OK;
     // LDS of the BCSR reduction: 4 waves x tiles x 4 registers x 64 lanes
     constexpr int TILES = (sizeof(TV) == 2) ? BV : BV * BNL;
     constexpr int TP = TILES >= 2 ? TILES / 2 : 1;
     constexpr size_t ACC_B = (sizeof(TV) == 8) ? 8 : 4;
     const size_t lds = g_bcsr ? (size_t)4 * TP * 4 * 64 * ACC_B : 0;
+    // the BCSR-part's workgroups stay resident and stride over the units
+    // (the next unit's metadata is fetched while the current one runs):
+    // cap the part at what the GPU holds at once
+    if (g_bcsr && !q && bcsr_persistent()) {
+        static int resident = -1;  // per kernel instantiation
+        if (resident < 0) {
+            int nb = 0, dev = 0, cus = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &nb, reinterpret_cast<const void*>(&k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, false, true>), 256,
+                    lds) != hipSuccess)
+                nb = 0;
+            resident = nb > 0 ? nb * cus : 0;
+        }
+        if (resident > 0 && (int64_t)g_bcsr > resident) g_bcsr = pad8(resident);
+    }
+    // calibrated partition (Eq. 3 analogue): caps on each part's workgroups
+    if (X.part_csr > 0 && g_csr > (uint32_t)X.part_csr) g_csr = pad8(X.part_csr);
+    if (X.part_bcsr > 0 && g_bcsr > (uint32_t)X.part_bcsr) g_bcsr = pad8(X.part_bcsr);
     if (q) {
         // geometry of the default launch and how many of its workgroups fit on a CU
         q->g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
@@ -498,7 +568,14 @@ int launch_cfg(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuery*
     }
     const dim3 grid(g_bcsr + g_csr), block(256);
     const int rm = xcd_remap_mode();
-    if (g_bcsr && g_csr) {
+    if (g_bcsr && g_csr && hybrid_launch_mode() == 2) {
+        // the two parts as two kernels, each with its own register budget
+        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, false, true>), dim3(g_bcsr), block, lds, s, ca, ba,
+                           d, g_bcsr, 0u, rm);
+        HIP_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, false>), dim3(g_csr), block, 0, s, ca, ba, d,
+                           0u, g_csr, rm);
+    } else if (g_bcsr && g_csr) {
         hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, true>), grid, block, lds, s, ca, ba, d,
                            g_bcsr, g_csr, rm);
     } else if (g_csr) {

@@ -61,6 +61,27 @@ def test_backward_integer_bitwise(split):
     assert np.array_equal(dA.double().cpu().numpy(), oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, G, B))
 
 
+@pytest.mark.parametrize("split", SPLITS)
+def test_concurrent_backward_equals_sequential(split, monkeypatch):
+    """With HSPMM_BWD_CONCURRENT=1 the SDDMM runs on the plan's side stream
+    beside dB; both gradients are bitwise those of the sequential backward,
+    on two calls in a row (the side stream and its events are reused)."""
+    print(f"concurrent backward split={split}", flush=True)
+    a = gen.random_csr(5, 700, 650, 0.03)
+    g = np.random.default_rng(8)
+    B = to_dev(g.standard_normal((a.k, 48)), torch.float32)
+    G = to_dev(g.standard_normal((a.m, 48)), torch.float32)
+    plan = make_plan(hs, a, torch.float32, split, backward=True)
+    monkeypatch.delenv("HSPMM_BWD_CONCURRENT", raising=False)
+    ref = [t.cpu().numpy() for t in plan.backward(B, G)]
+    monkeypatch.setenv("HSPMM_BWD_CONCURRENT", "1")
+    for _ in range(2):
+        got = [t.cpu().numpy() for t in plan.backward(B, G)]
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    assert oracle.rel_err(ref[1], oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx,
+                                               G.double().cpu().numpy(), B.double().cpu().numpy())) <= 1e-5
+
+
 def test_transposed_format_equals_cpu_transpose():
     from oracle import loops_ref as L
     a = gen.random_csr(4, 120, 90, 0.1)
