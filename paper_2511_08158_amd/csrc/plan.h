@@ -33,6 +33,7 @@ struct SubPlan {
     // BCSR-part (Alg. 1 step 2): B_r x 1 tiles, values packed in MFMA lane order
     int64_t rb_bcsr = 0, nblk = 0, nblk_pad = 0, nnz_bcsr = 0;
     DevBuf bcsr_rb, blk_ptr, blk_cnt, blk_col, blk_val, blk_src;
+    DevBuf blk_mask;      // uint16 [nblk_pad]: bit i set when row i of the tile holds an entry
     std::vector<int32_t> h_bcsr_rb, h_blk_ptr, h_blk_cnt;
 
     DevBuf scale;                 // double [nrb] (scaled sub-plans only)

@@ -178,6 +178,16 @@ __global__ void k_build_bcsr(const int32_t* __restrict__ ord, const int32_t* __r
     }
 }
 
+// occupancy mask of every tile from its slot -> entry map
+__global__ void k_build_mask(const int32_t* __restrict__ blk_src, int64_t nblk_pad, bool half,
+                             uint16_t* __restrict__ blk_mask) {
+    GRID_STRIDE(t, nblk_pad) {
+        uint32_t mk = 0;
+        for (int i = 0; i < 16; ++i) mk |= (blk_src[pack_index(t, i, half)] >= 0 ? 1u : 0u) << i;
+        blk_mask[t] = (uint16_t)mk;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // values
 // ---------------------------------------------------------------------------
@@ -569,6 +579,10 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
         hipLaunchKernelGGL(k_build_bcsr, dim3(grid_for(n)), dim3(kThreads), 0, s, ord.as<int32_t>(),
                            hd.as<int32_t>(), hx.as<int32_t>(), row_of, col, src, rp, d_slot.as<int32_t>(),
                            X.blk_ptr.as<int32_t>(), n, half, X.blk_col.as<int32_t>(), X.blk_src.as<int32_t>());
+        HIP_LAUNCH_CHECK();
+        HSPMM_TRY(al.alloc(X.blk_mask, (size_t)X.nblk_pad * 2));
+        hipLaunchKernelGGL(k_build_mask, dim3(grid_for(X.nblk_pad)), dim3(kThreads), 0, s, X.blk_src.as<int32_t>(),
+                           X.nblk_pad, half, static_cast<uint16_t*>(X.blk_mask.ptr));
         HIP_LAUNCH_CHECK();
         HIP_TRY(hipStreamSynchronize(s));
         al.free(d_slot);

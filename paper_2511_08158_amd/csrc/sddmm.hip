@@ -25,9 +25,9 @@ struct SddArgs {
     const int32_t* blk_ptr;
     const int32_t* blk_cnt;
     const int32_t* blk_col;
-    const int32_t* blk_src;
+    const uint16_t* blk_mask;  // rows of each tile that hold an entry
+    const int32_t* canon_rp;   // canonical row pointer of A
     int64_t n_rb;
-    bool half_pack;
     // dense operands
     const void* B;
     int64_t ldb;
@@ -37,11 +37,6 @@ struct SddArgs {
     int64_t m;
     void* dA;
 };
-
-__host__ __device__ inline int64_t pack_index(int64_t blk, int i, bool half) {
-    if (!half) return blk * 16 + i;
-    return (blk >> 5) * 512 + ((blk & 31) >> 3) * 128 + i * 8 + (blk & 7);
-}
 
 template <class T, int N>
 __device__ inline void load_as(const T* p, typename Elem<T>::acc_t (&out)[N]) {
@@ -154,8 +149,39 @@ __device__ inline d4_t mfma4(double a, double b, d4_t c) {
 template <class T> struct AccOf;
 template <> struct AccOf<float> { typedef f4_t type; };
 template <> struct AccOf<double> { typedef d4_t type; };
-template <class T> __device__ inline int out_row(int g, int r) { return 4 * g + r; }
-template <> __device__ inline int out_row<double>(int g, int r) { return g + 4 * r; }
+template <class T> __host__ __device__ constexpr int out_row(int g, int r) { return 4 * g + r; }
+template <> __host__ __device__ constexpr int out_row<double>(int g, int r) { return g + 4 * r; }
+// inverse of out_row: the lane group and register that hold row R
+template <class T> __host__ __device__ constexpr int row_group(int R) { return R >> 2; }
+template <> __host__ __device__ constexpr int row_group<double>(int R) { return R & 3; }
+template <class T> __host__ __device__ constexpr int row_reg(int R) { return R & 3; }
+template <> __host__ __device__ constexpr int row_reg<double>(int R) { return R >> 2; }
+
+// Destinations of a chunk's results.  The tiles of a row block are sorted by
+// column, and so are the entries of each canonical row, so the entry of row
+// R in tile t sits at canon_rp[R] + (number of earlier tiles of the row
+// block that hold row R).  A round is the 64 consecutive tiles whose four
+// chunks go to the four waves; lane l holds the occupancy mask of tile l of
+// the round, and one ballot per row gives that row's presence in all 64.
+// Each wave walks every round up to its own chunk and keeps the running
+// count of its lanes' four rows: 2 bytes of mask per tile instead of 16
+// stored destinations.
+template <class TG>
+__device__ inline void chunk_dst(uint32_t mt, int w, int j, int q, const int32_t (&rbase)[4], int32_t (&run)[4],
+                                 int32_t (&dst)[4]) {
+    const uint32_t below = (1u << j) - 1u;
+#pragma unroll
+    for (int R = 0; R < 16; ++R) {
+        const uint64_t b = __ballot((mt >> R) & 1u);
+        const uint32_t bits = (uint32_t)(b >> (16 * w)) & 0xffffu;
+        const int before = __popcll(b & ((1ull << (16 * w)) - 1ull));
+        const int r = row_reg<TG>(R);
+        if (q == row_group<TG>(R)) {
+            dst[r] = ((bits >> j) & 1u) ? rbase[r] + run[r] + before + __popc(bits & below) : -1;
+            run[r] += __popcll(b);
+        }
+    }
+}
 
 // One workgroup per row block.  K of the MFMA runs over the n columns:
 // lane (i, q) supplies columns kbase + q*VEC + v of dC row i and of B row j,
@@ -201,24 +227,35 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
     // occupancy, and no slower than 2
     constexpr int GB = (HSPMM_SDD_GATHER > 0 && HSPMM_SDD_GATHER < NKR) ? HSPMM_SDD_GATHER : NKR;
     static_assert(NKR % GB == 0, "gather batch must divide the cached steps");
+    // canonical position of the first entry of each of this lane's rows, and
+    // the entries of those rows in the tiles walked so far
+    int32_t rbase[4], run[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t row = (int64_t)rb * 16 + out_row<TG>(q, r);
+        rbase[r] = a.canon_rp[row < a.m ? row : a.m];
+        run[r] = 0;
+    }
     for (int it0 = 0; 16 * w + 64 * it0 < cnt; it0 += 4) {
         // tile columns of this wave's next four chunks: lane l -> chunk it0 + l/16
         const int pre = 16 * w + 64 * (it0 + (lane >> 4)) + j;
         const int colreg = pre < cnt ? a.blk_col[b0 + pre] : 0;
-        for (int it = it0; it < it0 + 4; ++it) {
+        // occupancy masks of the next four rounds: lane l -> tile l of the round
+        uint32_t mk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int t = 64 * (it0 + k) + lane;
+            mk[k] = t < cnt ? a.blk_mask[b0 + t] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int it = it0 + k;
             const int c0 = 16 * w + 64 * it;
             if (c0 >= cnt) break;
+            const int bc = __shfl(colreg, (16 * k + j) & 63, 64);
             const bool bok = c0 + j < cnt;
-            const int bc = __shfl(colreg, (16 * (it - it0) + j) & 63, 64);
-            // destinations of this lane's four results, fetched before the
-            // products so their latency overlaps the gathers
             int32_t dst[4];
-            {
-                const int64_t blk = (int64_t)b0 + c0 + j;
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    dst[r] = bok ? a.blk_src[pack_index(blk, out_row<TG>(q, r), a.half_pack)] : -1;
-            }
+            chunk_dst<TG>(mk[k], w, j, q, rbase, run, dst);
             acc_v acc = acc_v{0, 0, 0, 0};
             if (cached) {
                 // the gathers of GB steps first, then their products
@@ -369,8 +406,8 @@ int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC,
     } else {
         SddArgs a{X.vr_start.as<int32_t>(), X.vr_end.as<int32_t>(), X.vr_row.as<int32_t>(), X.csr_col.as<int32_t>(),
                   X.csr_src.as<int32_t>(), X.n_vrows, X.bcsr_rb.as<int32_t>(), X.blk_ptr.as<int32_t>(),
-                  X.blk_cnt.as<int32_t>(), X.blk_col.as<int32_t>(), X.blk_src.as<int32_t>(), X.rb_bcsr,
-                  X.ct == HSPMM_F16 || X.ct == HSPMM_BF16, B, ldb, dC, lddc, n, X.m, target};
+                  X.blk_cnt.as<int32_t>(), X.blk_col.as<int32_t>(), static_cast<const uint16_t*>(X.blk_mask.ptr),
+                  p.canon_rp.as<int32_t>(), X.rb_bcsr, B, ldb, dC, lddc, n, X.m, target};
         const size_t eb = dtype_size(X.ct);
         const int rc = [&]() -> int {
             switch (X.ct) {

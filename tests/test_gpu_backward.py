@@ -82,6 +82,46 @@ def test_concurrent_backward_equals_sequential(split, monkeypatch):
                                                G.double().cpu().numpy(), B.double().cpu().numpy())) <= 1e-5
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16])
+def test_sddmm_wide_row_blocks(dtype):
+    """Row blocks with thousands of tiles (many rounds of 64 tiles per wave),
+    a ragged last row block, empty rows and unsorted duplicated input: the
+    BCSR-part's destinations (ranks from the tile occupancy masks) against
+    the oracle, and dA bitwise equal between the BCSR-only and CSR-only
+    plans in FP64 with integer values."""
+    print(f"sddmm wide row blocks dtype={dtype}", flush=True)
+    g = np.random.default_rng(17)
+    m, k, n = 45, 6000, 32
+    dens = np.where(np.arange(m) % 7 == 3, 0.0, g.uniform(0.02, 0.4, m))
+    rows, cols = [], []
+    for i in range(m):
+        c = np.flatnonzero(g.random(k) < dens[i])
+        rows.append(np.full(c.size, i)); cols.append(c)
+    rows = np.concatenate(rows); cols = np.concatenate(cols)
+    dup = g.choice(rows.size, 50, replace=False)
+    rows = np.concatenate([rows, rows[dup]]); cols = np.concatenate([cols, cols[dup]])
+    perm = g.permutation(rows.size)
+    rows, cols = rows[perm], cols[perm]
+    order = np.argsort(rows, kind="stable")
+    rows, cols = rows[order], cols[order]          # rows grouped, columns unsorted
+    row_ptr = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=m))]).astype(np.int32)
+    vals = g.integers(-3, 4, rows.size).astype(float)
+    a = gen.Csr(m, k, row_ptr, cols.astype(np.int32), vals)
+    B = g.integers(-3, 4, (k, n)).astype(float)
+    G = g.integers(-3, 4, (m, n)).astype(float)
+    od = torch.float64 if dtype == torch.float64 else torch.float32
+    plan = make_plan(hs, a, dtype, "bcsr")
+    assert plan.info()["nblk"] > 4 * 64 * 4
+    _, dA = plan.backward(to_dev(B, dtype), to_dev(G, od), need_dB=False, need_dA=True)
+    torch.cuda.synchronize()
+    ref = oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, G, B)
+    assert np.array_equal(dA.double().cpu().numpy(), ref)
+    if dtype == torch.float64:
+        plan_c = make_plan(hs, a, dtype, "csr")
+        _, dA_c = plan_c.backward(to_dev(B, dtype), to_dev(G, od), need_dB=False, need_dA=True)
+        assert np.array_equal(dA_c.cpu().numpy(), dA.cpu().numpy())
+
+
 def test_transposed_format_equals_cpu_transpose():
     from oracle import loops_ref as L
     a = gen.random_csr(4, 120, 90, 0.1)
