@@ -195,6 +195,11 @@ __device__ inline uint32_t xcd_remap(uint32_t id, uint32_t G, int mode) {
     return (id & 7u) * per + (id >> 3);
 }
 int xcd_remap_mode();
+
+// Index of the calling wave in its workgroup, as a value the compiler knows
+// to be uniform over the wave (loops bounded by it stay scalar loops, whose
+// memory waits the compiler can count precisely).
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 // 0 (default): one workgroup per row block of the BCSR-part; 1
 // (HSPMM_BCSR_PERSIST=1): resident workgroups that each take a contiguous
 // range of row blocks, prefetching the next one's metadata (measured

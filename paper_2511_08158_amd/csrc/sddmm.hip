@@ -195,7 +195,7 @@ template <class TB, class TG, int VEC, int NKR>
 __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
     typedef typename AccOf<TG>::type acc_v;
     if (slot >= a.n_rb) return;  // uniform over the workgroup
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane & 15, q = lane >> 4;
+    const int lane = threadIdx.x & 63, w = wave_id(), j = lane & 15, q = lane >> 4;
     const int rb = a.rb[slot];
     const int b0 = a.blk_ptr[slot];
     const int cnt = a.blk_cnt[slot];
@@ -317,7 +317,7 @@ template <class TB, class TG, int VEC, int LPR, int BVEC, int NKR, bool DO_CSR, 
 __global__ __launch_bounds__(256) void k_sddmm(SddArgs a, uint32_t g_bcsr, uint32_t g_csr, int remap) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t bid = blockIdx.x;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     if (bid < g_bcsr) {
         if constexpr (DO_BCSR)
             sdd_bcsr_wg<TB, TG, BVEC, NKR>(a, (int64_t)xcd_remap(bid, g_bcsr, remap),

@@ -193,43 +193,46 @@ struct StepRegs {
     T bv[kStepBatch][NL][VEC];
 };
 
-// Operands of this wave's K steps in rounds r .. r + kStepBatch - 1
-// (zero-filled, without memory access, past the row block's last tile).
+// Operands of this wave's K steps in rounds r .. r + kStepBatch - 1.  The
+// loads are unconditional, so the compiler can count them precisely and
+// the MFMAs of one batch wait only for their own operands, not for the
+// batch loaded after them: a round past the wave's last one reloads the
+// last round (never used), a tile past the row block's end reads its
+// zero-valued padding slot and row 0 of B (0 * finite = 0), and a column
+// past n reads column 0 into a result column that is never stored.
 // The packed values are read once, so they bypass the caches' reuse
 // policy (non-temporal) and leave L2 to the gathered rows of B.
 template <class T, int VEC, int NL>
 __device__ inline void load_steps(const T* __restrict__ vals, const T* __restrict__ B, int64_t ldb, int64_t n,
-                                  int b0, int cnt, int w, int kq, int lane, int colreg, int j0, int jend, int r,
+                                  int b0, int w, int kq, int lane, int colreg, int j0, int jlast, int r,
                                   int64_t cbase, StepRegs<T, VEC, NL>& o) {
 #pragma unroll
     for (int s = 0; s < kStepBatch; ++s) {
-        const int rr = r + s;
+        const int rr = min(r + s, jlast);
         const int step0 = 16 * rr + 4 * w;
-        const bool step_ok = rr < jend && step0 < cnt;
-        const bool ok = step_ok && step0 + kq < cnt;
         const int bc = __shfl(colreg, (4 * (rr - j0) + kq) & 63, 64);
-        o.av[s] = step_ok ? __builtin_nontemporal_load(vals + (int64_t)(b0 + step0) * 16 + lane) : T(0);
+        o.av[s] = __builtin_nontemporal_load(vals + (int64_t)(b0 + step0) * 16 + lane);
 #pragma unroll
         for (int h = 0; h < NL; ++h) {
             const int64_t col = cbase + (int64_t)h * 16 * VEC;
-            if (ok && col < n) {
-                load_vec<T, VEC>(B + (int64_t)bc * ldb + col, o.bv[s][h]);
-            } else {
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) o.bv[s][h][v] = T(0);
-            }
+            load_vec<T, VEC>(B + (int64_t)bc * ldb + (col < n ? col : 0), o.bv[s][h]);
         }
     }
 }
 
+// MFMAs of the batch's rounds r .. r + kStepBatch - 1; a round at or past
+// jend holds a reloaded copy, whose A operand is replaced by zero (a select,
+// not a branch, so the loop body stays one block)
 template <class T, class ACC, int VEC, int NL>
-__device__ inline void mfma_steps(const StepRegs<T, VEC, NL>& o, ACC (&acc)[VEC * NL]) {
+__device__ inline void mfma_steps(const StepRegs<T, VEC, NL>& o, ACC (&acc)[VEC * NL], int r, int jend) {
 #pragma unroll
-    for (int s = 0; s < kStepBatch; ++s)
+    for (int s = 0; s < kStepBatch; ++s) {
+        const T a = r + s < jend ? o.av[s] : T(0);
 #pragma unroll
         for (int h = 0; h < NL; ++h)
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[h * VEC + v] = mfma4(o.av[s], o.bv[s][h][v], acc[h * VEC + v]);
+            for (int v = 0; v < VEC; ++v) acc[h * VEC + v] = mfma4(a, o.bv[s][h][v], acc[h * VEC + v]);
+    }
 }
 
 // One workgroup (4 waves) per (row block, column panel).  The row block's
@@ -253,7 +256,7 @@ __device__ inline UnitMeta bcsr_meta(const BcsrArgs& a, int64_t unit) {
     UnitMeta m{0, 0, 0, 0, 0, false};
     const int64_t slot = unit / a.n_panels;
     if (slot >= a.n_rb) return m;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_id();
     m.valid = true;
     m.panel = (int)(unit - slot * a.n_panels);
     m.rb = a.rb[slot];
@@ -270,7 +273,7 @@ __device__ void bcsr_wg_f(const BcsrArgs& a, const DenseArgs& d, const UnitMeta&
     constexpr int PANEL = 16 * VEC * NL;
     constexpr int TILES = VEC * NL;
     if (!um.valid) return;  // uniform over the workgroup
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane & 15, kq = lane >> 4;
+    const int lane = threadIdx.x & 63, w = wave_id(), j = lane & 15, kq = lane >> 4;
     const int rb = um.rb;
     const int b0 = um.b0;
     const int cnt = um.cnt;
@@ -281,24 +284,34 @@ __device__ void bcsr_wg_f(const BcsrArgs& a, const DenseArgs& d, const UnitMeta&
 #pragma unroll
     for (int t = 0; t < TILES; ++t) acc[t] = acc_v{0, 0, 0, 0};
 
-    const int nrounds = (cnt + 15) >> 4;  // a round = 16 tiles = one step per wave
-    for (int j0 = 0; j0 < nrounds; j0 += 16) {
+    // a round = 16 tiles = one step per wave; this wave's step of round rr
+    // starts at tile 16 rr + 4 w, so it has rounds 0 .. nr_w - 1
+    const int nr_w = cnt > 4 * w ? (cnt - 4 * w + 15) >> 4 : 0;
+    for (int j0 = 0; j0 < nr_w; j0 += 16) {
         int colreg = um.colreg;
         if (j0 > 0) {
             const int pre = 16 * (j0 + (lane >> 2)) + 4 * w + (lane & 3);
             colreg = pre < cnt ? a.blk_col[b0 + pre] : 0;
         }
-        const int jend = min(nrounds, j0 + 16);
+        const int jend = min(nr_w, j0 + 16);
         StepRegs<T, VEC, NL> x, y;
-        load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend, j0, cbase, x);
+        load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, w, kq, lane, colreg, j0, jend - 1, j0, cbase, x);
+        // the scheduling barriers keep each batch's loads ahead of the
+        // previous batch's MFMAs (the compiler would otherwise sink them to
+        // their use to save registers, serialising load and compute)
+        // (a body without an early exit: the batch after the last round is
+        // loaded from clamped addresses and multiplied by zero)
         for (int jr = j0; jr < jend; jr += 2 * kStepBatch) {
-            load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend, jr + kStepBatch,
+            load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, w, kq, lane, colreg, j0, jend - 1, jr + kStepBatch,
                                    cbase, y);
-            mfma_steps<T, acc_v, VEC, NL>(x, acc);
-            if (jr + kStepBatch >= jend) break;
-            load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, cnt, w, kq, lane, colreg, j0, jend,
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_steps<T, acc_v, VEC, NL>(x, acc, jr, jend);
+            __builtin_amdgcn_sched_barrier(0);
+            load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, w, kq, lane, colreg, j0, jend - 1,
                                    jr + 2 * kStepBatch, cbase, x);
-            mfma_steps<T, acc_v, VEC, NL>(y, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_steps<T, acc_v, VEC, NL>(y, acc, jr + kStepBatch, jend);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     // fixed-order reduction of the four partial tiles, in two passes over
@@ -360,7 +373,7 @@ __device__ void bcsr_wg_h(const BcsrArgs& a, const DenseArgs& d, int64_t unit, f
     const int64_t slot = unit / a.n_panels;
     if (slot >= a.n_rb) return;
     const int panel = (int)(unit - slot * a.n_panels);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane & 15, g = lane >> 4;
+    const int lane = threadIdx.x & 63, w = wave_id(), j = lane & 15, g = lane >> 4;
     const int rb = a.rb[slot];
     const int b0 = a.blk_ptr[slot];
     const int cnt = a.blk_cnt[slot];
@@ -451,7 +464,7 @@ __attribute__((amdgpu_waves_per_eu(DO_CSR && DO_BCSR ? bcsr_waves_per_simd<TV, V
 void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseArgs da, uint32_t g_bcsr, uint32_t g_csr, int remap) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t bid = blockIdx.x;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     if (bid < g_bcsr) {
         if constexpr (DO_BCSR) {
             // g_bcsr workgroups stride over the row-block units (one unit
