@@ -176,10 +176,11 @@ __device__ inline void chunk_dst(uint32_t mt, int w, int j, int q, const int32_t
         const uint32_t bits = (uint32_t)(b >> (16 * w)) & 0xffffu;
         const int before = __popcll(b & ((1ull << (16 * w)) - 1ull));
         const int r = row_reg<TG>(R);
-        if (q == row_group<TG>(R)) {
-            dst[r] = ((bits >> j) & 1u) ? rbase[r] + run[r] + before + __popc(bits & below) : -1;
-            run[r] += __popcll(b);
-        }
+        // selects, not branches: the lanes of group row_group(R) own row R
+        const bool mine = q == row_group<TG>(R);
+        const int d = ((bits >> j) & 1u) ? rbase[r] + run[r] + before + __popc(bits & below) : -1;
+        dst[r] = mine ? d : dst[r];
+        run[r] += mine ? __popcll(b) : 0;
     }
 }
 
@@ -254,34 +255,30 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
             if (c0 >= cnt) break;
             const int bc = __shfl(colreg, (16 * k + j) & 63, 64);
             const bool bok = c0 + j < cnt;
-            int32_t dst[4];
+            int32_t dst[4] = {-1, -1, -1, -1};
             chunk_dst<TG>(mk[k], w, j, q, rbase, run, dst);
             acc_v acc = acc_v{0, 0, 0, 0};
             if (cached) {
-                // the gathers of GB steps first, then their products
-#pragma unroll
-                for (int s0 = 0; s0 < NKR; s0 += GB) {
+                // the gathers of GB steps first, then their products.  The
+                // gathers are unconditional: a tile past the row block's end
+                // reads row 0 of B (its results have no destination), and a
+                // column past n reads column 0 against the zero padding of
+                // the dC slab in LDS
+                for (int s0 = 0; s0 < nsteps; s0 += GB) {
                     TG bv[GB][VEC];
 #pragma unroll
                     for (int t = 0; t < GB; ++t) {
-                        const int s = s0 + t;
-                        const int64_t c = (int64_t)s * STEP + q * VEC;
-                        if (s < nsteps && bok && c < a.n) {
-                            load_as<TB, VEC>(B + (int64_t)bc * a.ldb + c, bv[t]);
-                        } else {
-#pragma unroll
-                            for (int v = 0; v < VEC; ++v) bv[t][v] = TG(0);
-                        }
+                        const int64_t c = (int64_t)(s0 + t) * STEP + q * VEC;
+                        load_as<TB, VEC>(B + (int64_t)bc * a.ldb + (c < a.n ? c : 0), bv[t]);
                     }
 #pragma unroll
-                    for (int t = 0; t < GB; ++t)
-                        if (s0 + t < nsteps) {
-                            TG gv[VEC];
+                    for (int t = 0; t < GB; ++t) {
+                        TG gv[VEC];
 #pragma unroll
-                            for (int v = 0; v < VEC; ++v) gv[v] = gl_row[(s0 + t) * STEP + v];
+                        for (int v = 0; v < VEC; ++v) gv[v] = gl_row[(s0 + t) * STEP + v];
 #pragma unroll
-                            for (int v = 0; v < VEC; ++v) acc = mfma4(gv[v], bv[t][v], acc);
-                        }
+                        for (int v = 0; v < VEC; ++v) acc = mfma4(gv[v], bv[t][v], acc);
+                    }
                 }
             } else {
                 for (int s = 0; s < nsteps; ++s) {
