@@ -493,6 +493,11 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
     X.seg = seg;
     std::vector<int32_t> vs, ve, vo, vrow, lrow, lfirst, lcnt;
     int64_t nparts = 0;
+    // one list in row order, a long row's segments in its place: each XCD
+    // takes a contiguous range of the list, so any cluster of long rows
+    // (all of them first, say) would load one XCD with most of the work;
+    // neighbouring rows also share gathered rows of B (ordering short rows
+    // by length to even out lane groups measured slower on every workload)
     for (int64_t r = 0; r < X.rows_csr; ++r) {
         const int32_t lo = cptr[r], hi = cptr[r + 1];
         if (hi - lo > seg) {
@@ -508,18 +513,12 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
                 ++c;
             }
             lcnt.push_back(c);
+        } else {
+            vs.push_back(lo);
+            ve.push_back(hi);
+            vo.push_back(rows[r]);
+            vrow.push_back(rows[r]);
         }
-    }
-    // short rows in row order: neighbouring rows share gathered rows of B
-    // (ordering them by length to even out lane groups measured slower on
-    // every workload, banded and power-law alike)
-    for (int64_t r = 0; r < X.rows_csr; ++r) {
-        const int32_t lo = cptr[r], hi = cptr[r + 1];
-        if (hi - lo > seg) continue;
-        vs.push_back(lo);
-        ve.push_back(hi);
-        vo.push_back(rows[r]);
-        vrow.push_back(rows[r]);
     }
     X.n_vrows = (int64_t)vs.size();
     X.n_long = (int64_t)lrow.size();

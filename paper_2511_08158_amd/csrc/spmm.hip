@@ -54,13 +54,18 @@ struct DenseArgs {
 
 template <class T, int N>
 __device__ inline void load_vec(const T* p, T (&out)[N]) {
-    if constexpr (N == 1) {
-        out[0] = *p;
-    } else {
-        typedef T V __attribute__((ext_vector_type(N)));
-        const V v = *reinterpret_cast<const V*>(p);
+    constexpr int C = (N * (int)sizeof(T) > 16) ? 16 / (int)sizeof(T) : N;  // 16-byte chunks
+    if constexpr (C == 1) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) out[i] = v[i];
+        for (int i = 0; i < N; ++i) out[i] = p[i];
+    } else {
+        typedef T V __attribute__((ext_vector_type(C)));
+#pragma unroll
+        for (int k = 0; k < N; k += C) {
+            const V v = *reinterpret_cast<const V*>(p + k);
+#pragma unroll
+            for (int i = 0; i < C; ++i) out[k + i] = v[i];
+        }
     }
 }
 
@@ -187,6 +192,12 @@ template <> __device__ inline int out_row<double>(int g, int r) { return g + 4 *
 #define HSPMM_STEP_BATCH 1
 #endif
 constexpr int kStepBatch = HSPMM_STEP_BATCH;
+#ifndef HSPMM_CSR_U
+#define HSPMM_CSR_U 8
+#endif
+#ifndef HSPMM_F32_CSR_VEC8
+#define HSPMM_F32_CSR_VEC8 0
+#endif
 template <class T, int VEC, int NL>
 struct StepRegs {
     T av[kStepBatch];
@@ -496,7 +507,7 @@ void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseArgs da, uint32_t g_bcsr, uint32_t g
             const int64_t waves = (ca.n_vrows + R - 1) / R;
             for (int64_t wave = (int64_t)xcd_remap(bid - g_bcsr, g_csr, remap) * 4 + w; wave < waves;
                  wave += (int64_t)g_csr * 4)
-                csr_wave<TV, TB, TC, VEC, LPR, (DO_BCSR ? 4 : 8)>(ca, da, wave);
+                csr_wave<TV, TB, TC, VEC, LPR, (DO_BCSR ? 4 : HSPMM_CSR_U)>(ca, da, wave);
         }
     }
 }
@@ -643,6 +654,9 @@ int dispatch_dtype<float, float, float>(const SubPlan& X, const DenseArgs& d, bo
 #endif
         if (d.n <= 64) {
             HSPMM_LPR_SWITCH(lpr, return (launch_cfg<float, float, float, 4, LPR, 4, 1>(X, d, s, q)));
+        } else if (HSPMM_F32_CSR_VEC8 && d.n % 8 == 0) {
+            HSPMM_LPR_SWITCH(lpr_for(d.n, 8),
+                             return (launch_cfg<float, float, float, 8, LPR, 4, HSPMM_F32_NL>(X, d, s, q)));
         } else {
             HSPMM_LPR_SWITCH(lpr, return (launch_cfg<float, float, float, 4, LPR, 4, HSPMM_F32_NL>(X, d, s, q)));
         }
