@@ -496,8 +496,7 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
     // one list in row order, a long row's segments in its place: each XCD
     // takes a contiguous range of the list, so any cluster of long rows
     // (all of them first, say) would load one XCD with most of the work;
-    // neighbouring rows also share gathered rows of B (ordering short rows
-    // by length to even out lane groups measured slower on every workload)
+    // neighbouring rows also share gathered rows of B
     for (int64_t r = 0; r < X.rows_csr; ++r) {
         const int32_t lo = cptr[r], hi = cptr[r + 1];
         if (hi - lo > seg) {
@@ -519,6 +518,46 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
             vo.push_back(rows[r]);
             vrow.push_back(rows[r]);
         }
+    }
+    // A lane group takes one virtual row and a wave as many as it has lane
+    // groups, so a wave runs as long as its longest row.  Within windows of
+    // consecutive virtual rows, order them by length class floor(log2 len),
+    // longest first and stable: the rows of a wave then have lengths within
+    // a factor of two, rows of one class keep their order (and the B rows
+    // neighbouring rows share), and a window spans at most 1/32 of the list
+    // so every XCD's contiguous range keeps its share of long rows.
+    // Measured: power law FP16 fwd+bwd 2.05 -> 3.6 TFLOP/s, GCN 4.1 -> 4.5,
+    // block stencil unchanged (one length class); a sort over the whole
+    // list clusters the long rows on one XCD (3x slower), exact lengths
+    // break the stencil's row order (CSR-part 15 % slower).
+#ifndef HSPMM_SORT_WINDOW
+#define HSPMM_SORT_WINDOW 8192
+#endif
+    int64_t window = HSPMM_SORT_WINDOW;
+    while (window > 64 && window * 32 > (int64_t)vs.size()) window >>= 1;
+    if (window > 1) {
+        auto len_class = [&](int32_t x) -> int32_t {
+            const int32_t len = ve[x] - vs[x];
+            int32_t c = 0;
+            while ((len >> c) > 1) ++c;
+            return c;
+        };
+        std::vector<int32_t> idx(vs.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int32_t)i;
+        for (size_t w0 = 0; w0 < idx.size(); w0 += (size_t)window) {
+            const size_t w1 = std::min(idx.size(), w0 + (size_t)window);
+            std::stable_sort(idx.begin() + w0, idx.begin() + w1,
+                             [&](int32_t x, int32_t y) { return len_class(x) > len_class(y); });
+        }
+        auto apply = [&](std::vector<int32_t>& v) {
+            std::vector<int32_t> t(v.size());
+            for (size_t i = 0; i < idx.size(); ++i) t[i] = v[idx[i]];
+            v.swap(t);
+        };
+        apply(vs);
+        apply(ve);
+        apply(vo);
+        apply(vrow);
     }
     X.n_vrows = (int64_t)vs.size();
     X.n_long = (int64_t)lrow.size();
