@@ -192,8 +192,17 @@ template <> __device__ inline int out_row<double>(int g, int r) { return g + 4 *
 #define HSPMM_STEP_BATCH 1
 #endif
 constexpr int kStepBatch = HSPMM_STEP_BATCH;
+// gathers a CSR lane group keeps in flight: 4, or 2 for FP16/BF16 lane
+// groups of 8 lanes or fewer.  Measured: power law FP16 n = 64 (8 lanes)
+// forward 602 / 529 / 442 us at 8 / 4 / 2; block stencil FP32 n = 128 (32
+// lanes) CSR-only forward 51.3 / 49.7 / 54.3 us; GCN indifferent; on the
+// FP32 structure sweep 2 instead of 4 loses 6 % at n = 16 (4 lanes, up to
+// 2.4x on a banded matrix with 54 entries per row).
 #ifndef HSPMM_CSR_U
-#define HSPMM_CSR_U 8
+#define HSPMM_CSR_U 4
+#endif
+#ifndef HSPMM_CSR_U_NARROW
+#define HSPMM_CSR_U_NARROW 2
 #endif
 #ifndef HSPMM_F32_CSR_VEC8
 #define HSPMM_F32_CSR_VEC8 0
@@ -453,11 +462,10 @@ __device__ void bcsr_wg_h(const BcsrArgs& a, const DenseArgs& d, int64_t unit, f
 // ---------------------------------------------------------------------------
 // DO_CSR / DO_BCSR compile a part out when the plan has none of it, so a
 // one-part plan does not pay the other part's register footprint.  When both
-// parts are compiled in, the CSR lane groups keep fewer gathers in flight
-// (4 instead of 8) and the kernel is held to the waves per SIMD that the
-// BCSR-only kernel reaches: the BCSR-part is latency-bound and loses in
-// proportion to lost occupancy, while the CSR-part's lost depth per wave is
-// made up by the extra waves.
+// parts are compiled in, the kernel is held to the waves per SIMD that the
+// BCSR-only kernel reaches: the BCSR-part loses in proportion to lost
+// occupancy, while the CSR code, compiled into a tighter register budget,
+// makes up with the extra waves.
 template <class TV, int VEC, int BV, int BNL>
 constexpr int bcsr_waves_per_simd() {
     // register-limited occupancy of the BCSR-only instantiations on gfx950
@@ -507,7 +515,8 @@ void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseArgs da, uint32_t g_bcsr, uint32_t g
             const int64_t waves = (ca.n_vrows + R - 1) / R;
             for (int64_t wave = (int64_t)xcd_remap(bid - g_bcsr, g_csr, remap) * 4 + w; wave < waves;
                  wave += (int64_t)g_csr * 4)
-                csr_wave<TV, TB, TC, VEC, LPR, (DO_BCSR ? 4 : HSPMM_CSR_U)>(ca, da, wave);
+                csr_wave<TV, TB, TC, VEC, LPR, (sizeof(TV) == 2 && LPR <= 8 ? HSPMM_CSR_U_NARROW : HSPMM_CSR_U)>(
+                    ca, da, wave);
         }
     }
 }
