@@ -64,15 +64,17 @@ int calibrate(Plan& p, int64_t n, const void* B, int64_t ldb, void* C, int64_t l
     out.x_max = xmax;
     out.y_max = ymax;
 
-    // candidate set: fractions of T for each present part
-    const double fr[] = {0.125, 0.25, 0.375, 0.5, 0.75, 1.0};
+    // candidate set: fractions of each present part's default size, pairs
+    // within the budget x + y <= T (5 x 5 at most, below HSPMM_CALIB_MAX)
+    const double fr[] = {0.125, 0.25, 0.5, 0.75, 1.0};
     std::vector<std::pair<int, int>> cand;
-    auto clampx = [&](double f) { return std::max(1, std::min(xmax, (int)std::lround(f * T))); };
-    auto clampy = [&](double f) { return std::max(1, std::min(ymax, (int)std::lround(f * T))); };
+    auto clampx = [&](double f) { return std::max(1, (int)std::lround(f * xmax)); };
+    auto clampy = [&](double f) { return std::max(1, (int)std::lround(f * ymax)); };
     if (has_c && has_b) {
         for (double fx : fr)
             for (double fy : fr)
-                if (fx + fy <= 1.0 + 1e-9) cand.emplace_back(clampx(fx), clampy(fy));
+                if (clampx(fx) + clampy(fy) <= T) cand.emplace_back(clampx(fx), clampy(fy));
+        if (cand.empty()) cand.emplace_back(1, 1);
     } else if (has_c) {
         for (double fx : fr) cand.emplace_back(clampx(fx), 0);
     } else {

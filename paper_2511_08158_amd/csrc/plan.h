@@ -35,6 +35,7 @@ struct SubPlan {
     DevBuf bcsr_rb, blk_ptr, blk_cnt, blk_col, blk_val, blk_src;
     DevBuf blk_mask;      // uint16 [nblk_pad]: bit i set when row i of the tile holds an entry
     std::vector<int32_t> h_bcsr_rb, h_blk_ptr, h_blk_cnt;
+    int64_t max_rb_tiles = 0;  // most tiles in one row block of the BCSR-part
 
     DevBuf scale;                 // double [nrb] (scaled sub-plans only)
 

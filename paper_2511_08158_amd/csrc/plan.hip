@@ -589,12 +589,14 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
     std::vector<int32_t> rb_slot(nrb, -1);
     int64_t pad_acc = 0;
     X.nblk = 0;
+    X.max_rb_tiles = 0;
     X.nnz_bcsr = 0;
     for (int64_t q = 0; q < nrb; ++q) {
         if (!X.h_cls[q]) continue;
         rb_slot[q] = (int32_t)X.h_bcsr_rb.size();
         X.h_bcsr_rb.push_back((int32_t)q);
         X.h_blk_cnt.push_back(X.h_rb_nblk[q]);
+        X.max_rb_tiles = std::max<int64_t>(X.max_rb_tiles, X.h_rb_nblk[q]);
         X.nblk += X.h_rb_nblk[q];
         X.nnz_bcsr += X.h_rb_nnz[q];
         pad_acc += ceil_div(X.h_rb_nblk[q], X.kc) * X.kc;

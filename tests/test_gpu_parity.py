@@ -127,6 +127,39 @@ def test_long_rows_are_split_deterministically():
     assert oracle.rel_err(C1, oracle_forward(a, B)) <= 1e-5
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_wide_row_blocks_forward(dtype):
+    """FP32/FP64 BCSR-parts run one wave per row block when every row block
+    has at most 2048 tiles and the four-wave split otherwise: a plan with one
+    row block of ~10,000 tiles (integer values, bitwise against the oracle)
+    and the same matrix without it (the one-wave form) give the oracle's
+    result, and so do both forms on a real-valued copy within tolerance."""
+    print(f"wide row blocks dtype={dtype}", flush=True)
+    g = np.random.default_rng(23)
+    m, k, n = 50, 12000, 40
+    dens = np.full(m, 0.004)
+    dens[16:32] = 0.1                      # row block 1: ~9,800 distinct columns
+    rows, cols = [], []
+    for i in range(m):
+        c = np.flatnonzero(g.random(k) < dens[i])
+        rows.append(np.full(c.size, i)); cols.append(c)
+    rows = np.concatenate(rows); cols = np.concatenate(cols)
+    vals = g.integers(-3, 4, rows.size).astype(float)
+    a = gen.csr_from_coo(m, k, rows, cols, vals)
+    B = g.integers(-3, 4, (k, n)).astype(float)
+    wide = make_plan(hs, a, dtype, "bcsr")
+    assert wide.info()["nblk"] > 2048
+    assert np.array_equal(_run(wide, B, dtype), oracle_forward(a, B))
+    keep = (rows < 16) | (rows >= 32)
+    a2 = gen.csr_from_coo(m, k, rows[keep], cols[keep], vals[keep])
+    narrow = make_plan(hs, a2, dtype, "bcsr")
+    assert np.array_equal(_run(narrow, B, dtype), oracle_forward(a2, B))
+    ar = gen.csr_from_coo(m, k, rows, cols, g.standard_normal(rows.size))
+    Br = g.standard_normal((k, n))
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    assert oracle.rel_err(_run(make_plan(hs, ar, dtype, "bcsr"), Br, dtype), oracle_forward(ar, Br)) <= tol
+
+
 # ---------------------------------------------------------------------------
 # the built format equals Alg. 1 replayed on the CPU
 # ---------------------------------------------------------------------------
