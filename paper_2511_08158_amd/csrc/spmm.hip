@@ -220,8 +220,8 @@ struct StepRegs {
 // last round (never used), a tile past the row block's end reads its
 // zero-valued padding slot and row 0 of B (0 * finite = 0), and a column
 // past n reads column 0 into a result column that is never stored.
-// The packed values are read once, so they bypass the caches' reuse
-// policy (non-temporal) and leave L2 to the gathered rows of B.
+// The packed values are loaded with the default cache policy: the
+// non-temporal hint measured 7 % (FP32) to 13 % (FP64) slower.
 template <class T, int VEC, int NL>
 __device__ inline void load_steps(const T* __restrict__ vals, const T* __restrict__ B, int64_t ldb, int64_t n,
                                   int b0, int w, int kq, int lane, int colreg, int j0, int jlast, int r,
@@ -231,7 +231,7 @@ __device__ inline void load_steps(const T* __restrict__ vals, const T* __restric
         const int rr = min(r + s, jlast);
         const int step0 = 16 * rr + 4 * w;
         const int bc = __shfl(colreg, (4 * (rr - j0) + kq) & 63, 64);
-        o.av[s] = __builtin_nontemporal_load(vals + (int64_t)(b0 + step0) * 16 + lane);
+        o.av[s] = vals[(int64_t)(b0 + step0) * 16 + lane];
 #pragma unroll
         for (int h = 0; h < NL; ++h) {
             const int64_t col = cbase + (int64_t)h * 16 * VEC;
@@ -385,7 +385,7 @@ __device__ inline void load_wave_steps(const T* __restrict__ vals, const T* __re
     for (int s = 0; s < kStepBatch; ++s) {
         const int ss = min(st + s, slast);
         const int bc = __shfl(colreg, (4 * (ss - s0) + q) & 63, 64);
-        o.av[s] = __builtin_nontemporal_load(vals + (int64_t)(b0 + 4 * ss) * 16 + lane);
+        o.av[s] = vals[(int64_t)(b0 + 4 * ss) * 16 + lane];
 #pragma unroll
         for (int h = 0; h < NL; ++h) {
             const int64_t col = cbase + (int64_t)h * 16 * VEC;
