@@ -207,10 +207,10 @@ constexpr int kStepBatch = HSPMM_STEP_BATCH;
 #ifndef HSPMM_F32_CSR_VEC8
 #define HSPMM_F32_CSR_VEC8 0
 #endif
-template <class T, int VEC, int NL>
+template <class T, int VEC, int NL, int SB = kStepBatch>
 struct StepRegs {
-    T av[kStepBatch];
-    T bv[kStepBatch][NL][VEC];
+    T av[SB];
+    T bv[SB][NL][VEC];
 };
 
 // Operands of this wave's K steps in rounds r .. r + kStepBatch - 1.  The
@@ -243,10 +243,10 @@ __device__ inline void load_steps(const T* __restrict__ vals, const T* __restric
 // MFMAs of the batch's rounds r .. r + kStepBatch - 1; a round at or past
 // jend holds a reloaded copy, whose A operand is replaced by zero (a select,
 // not a branch, so the loop body stays one block)
-template <class T, class ACC, int VEC, int NL>
-__device__ inline void mfma_steps(const StepRegs<T, VEC, NL>& o, ACC (&acc)[VEC * NL], int r, int jend) {
+template <class T, class ACC, int VEC, int NL, int SB>
+__device__ inline void mfma_steps(const StepRegs<T, VEC, NL, SB>& o, ACC (&acc)[VEC * NL], int r, int jend) {
 #pragma unroll
-    for (int s = 0; s < kStepBatch; ++s) {
+    for (int s = 0; s < SB; ++s) {
         const T a = r + s < jend ? o.av[s] : T(0);
 #pragma unroll
         for (int h = 0; h < NL; ++h)
@@ -325,12 +325,12 @@ __device__ void bcsr_wg_f(const BcsrArgs& a, const DenseArgs& d, const UnitMeta&
             load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, w, kq, lane, colreg, j0, jend - 1, jr + kStepBatch,
                                    cbase, y);
             __builtin_amdgcn_sched_barrier(0);
-            mfma_steps<T, acc_v, VEC, NL>(x, acc, jr, jend);
+            mfma_steps<T, acc_v, VEC, NL, kStepBatch>(x, acc, jr, jend);
             __builtin_amdgcn_sched_barrier(0);
             load_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, w, kq, lane, colreg, j0, jend - 1,
                                    jr + 2 * kStepBatch, cbase, x);
             __builtin_amdgcn_sched_barrier(0);
-            mfma_steps<T, acc_v, VEC, NL>(y, acc, jr + kStepBatch, jend);
+            mfma_steps<T, acc_v, VEC, NL, kStepBatch>(y, acc, jr + kStepBatch, jend);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -377,12 +377,12 @@ __device__ void bcsr_wg_f(const BcsrArgs& a, const DenseArgs& d, const UnitMeta&
 // on the block stencil FP32 n = 128: forward 34.9 -> 33.5 us, FP64 68.2 ->
 // 65.6 us against the four-wave split with its LDS reduction.
 constexpr int kWaveMaxTiles = 2048;
-template <class T, int VEC, int NL>
+template <class T, int VEC, int NL, int SB>
 __device__ inline void load_wave_steps(const T* __restrict__ vals, const T* __restrict__ B, int64_t ldb, int64_t n,
                                        int b0, int q, int lane, int colreg, int s0, int slast, int st,
-                                       int64_t cbase, StepRegs<T, VEC, NL>& o) {
+                                       int64_t cbase, StepRegs<T, VEC, NL, SB>& o) {
 #pragma unroll
-    for (int s = 0; s < kStepBatch; ++s) {
+    for (int s = 0; s < SB; ++s) {
         const int ss = min(st + s, slast);
         const int bc = __shfl(colreg, (4 * (ss - s0) + q) & 63, 64);
         o.av[s] = vals[(int64_t)(b0 + 4 * ss) * 16 + lane];
@@ -417,18 +417,21 @@ __device__ void bcsr_wave_f(const BcsrArgs& a, const DenseArgs& d, int64_t unit)
         // 16 steps = 64 tiles: lane l holds the column of tile 4 s0 + l
         const int colreg = 4 * s0 + lane < cnt ? a.blk_col[b0 + 4 * s0 + lane] : 0;
         const int send = min(nsteps, s0 + 16);
-        StepRegs<T, VEC, NL> x, y;
-        load_wave_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1, s0, cbase, x);
-        for (int sr = s0; sr < send; sr += 2 * kStepBatch) {
-            load_wave_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1, sr + kStepBatch,
-                                        cbase, y);
+        // steps per batch: 2 for FP64 (52.5 against 55.8 us on the stencil),
+        // 1 for FP32 (no gain from 2)
+        constexpr int SB = sizeof(T) == 8 ? 2 : 1;
+        StepRegs<T, VEC, NL, SB> x, y;
+        load_wave_steps<T, VEC, NL, SB>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1, s0, cbase, x);
+        for (int sr = s0; sr < send; sr += 2 * SB) {
+            load_wave_steps<T, VEC, NL, SB>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1, sr + SB, cbase,
+                                            y);
             __builtin_amdgcn_sched_barrier(0);
-            mfma_steps<T, acc_v, VEC, NL>(x, acc, sr, send);
+            mfma_steps<T, acc_v, VEC, NL, SB>(x, acc, sr, send);
             __builtin_amdgcn_sched_barrier(0);
-            load_wave_steps<T, VEC, NL>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1,
-                                        sr + 2 * kStepBatch, cbase, x);
+            load_wave_steps<T, VEC, NL, SB>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1, sr + 2 * SB,
+                                            cbase, x);
             __builtin_amdgcn_sched_barrier(0);
-            mfma_steps<T, acc_v, VEC, NL>(y, acc, sr + kStepBatch, send);
+            mfma_steps<T, acc_v, VEC, NL, SB>(y, acc, sr + SB, send);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -553,7 +556,7 @@ constexpr int bcsr_waves_per_simd() {
     // BF16 with 4 column groups is held one wave lower, where the fused
     // kernel fits without spilling
     if (sizeof(TV) == 2) return VEC == 1 ? 8 : (BV == 8 ? 4 : 5);
-    if (sizeof(TV) == 8) return VEC == 1 ? 4 : (BNL >= 2 ? (WAVE ? 5 : 4) : (WAVE ? 8 : 7));
+    if (sizeof(TV) == 8) return VEC == 1 ? 4 : (BNL >= 2 ? 4 : (WAVE ? 8 : 7));
     return VEC == 1 ? (WAVE ? 7 : 6) : (BNL >= 2 ? (WAVE ? 5 : 4) : 8);
 }
 
