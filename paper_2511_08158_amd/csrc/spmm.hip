@@ -540,6 +540,92 @@ __device__ void bcsr_wg_h(const BcsrArgs& a, const DenseArgs& d, int64_t unit, f
     store_vec<float, CPL>(static_cast<float*>(d.C) + row * d.ldc + cbase, o);
 }
 
+// One wave per (row block, column panel) for FP16 / BF16: the wave runs the
+// row block's 32-tile K steps itself, loading step s + 1 (tile columns,
+// packed values, the 8 gathered rows per lane) while the MFMAs of step s
+// run, and stores its accumulators directly.  Loads are unconditional: a
+// padding tile reads row 0 of B against zero values, a column group past n
+// reads column 0 into results that are not stored.
+template <class T, int CPL>
+struct HStep {
+    typename V8Of<T>::type av;
+    T raw[8][CPL];
+};
+
+template <class T, int CPL>
+__device__ inline void load_hstep(const BcsrArgs& a, const T* __restrict__ vals, const T* __restrict__ B,
+                                  int64_t ldb, int b0, int cnt, int step0, int lane, int g, int64_t col,
+                                  HStep<T, CPL>& o) {
+    typedef typename V8Of<T>::type v8;
+    const int pre = step0 + (lane & 31);
+    const int colreg = pre < cnt ? a.blk_col[b0 + pre] : 0;
+    o.av = *reinterpret_cast<const v8*>(vals + ((int64_t)(b0 + step0) * 16 + lane * 8));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int bc = __shfl(colreg, 8 * g + u, 64);
+        load_vec<T, CPL>(B + (int64_t)bc * ldb + col, o.raw[u]);
+    }
+}
+
+template <class T, int CPL>
+__device__ inline void mfma_hstep(const HStep<T, CPL>& o, f4_t (&acc)[CPL]) {
+    typedef typename V8Of<T>::type v8;
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) {
+        v8 bop;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bop[u] = o.raw[u][t];
+        acc[t] = mfma32(o.av, bop, acc[t]);
+    }
+}
+
+template <class T, int CPL>
+__device__ void bcsr_wave_h(const BcsrArgs& a, const DenseArgs& d, int64_t unit) {
+    constexpr int PANEL = 16 * CPL;
+    const int64_t slot = unit / a.n_panels;
+    if (slot >= a.n_rb) return;  // uniform over the wave
+    const int panel = (int)(unit - slot * a.n_panels);
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    const int rb = a.rb[slot];
+    const int b0 = a.blk_ptr[slot];
+    const int cnt = a.blk_cnt[slot];
+    const int64_t cbase = (int64_t)panel * PANEL + (int64_t)j * CPL;
+    const bool colok = cbase < d.n;
+    const int64_t col = colok ? cbase : 0;
+    const T* __restrict__ vals = static_cast<const T*>(a.val);
+    const T* __restrict__ B = static_cast<const T*>(d.B);
+    f4_t acc[CPL];
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) acc[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+    const int nsteps = (cnt + 31) >> 5;
+    HStep<T, CPL> x, y;
+    load_hstep<T, CPL>(a, vals, B, d.ldb, b0, cnt, 0, lane, g, col, x);
+    for (int s = 0; s < nsteps; s += 2) {
+        // the step after the last one reloads the last (multiplied by zero)
+        const int s1 = min(s + 1, nsteps - 1), s2 = min(s + 2, nsteps - 1);
+        load_hstep<T, CPL>(a, vals, B, d.ldb, b0, cnt, 32 * s1, lane, g, col, y);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_hstep<T, CPL>(x, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        load_hstep<T, CPL>(a, vals, B, d.ldb, b0, cnt, 32 * s2, lane, g, col, x);
+        __builtin_amdgcn_sched_barrier(0);
+        if (s + 1 >= nsteps) y.av = typename V8Of<T>::type{};  // a select, not a branch
+        mfma_hstep<T, CPL>(y, acc);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (!colok) return;
+    const float sc = d.scale ? (float)d.scale[rb] : 1.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t row = (int64_t)rb * 16 + 4 * g + r;
+        if (row >= d.m) continue;
+        float o[CPL];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) o[t] = acc[t][r] * sc;
+        store_vec<float, CPL>(static_cast<float*>(d.C) + row * d.ldc + cbase, o);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // fused launch: workgroups [0, g_bcsr) run the BCSR-part, the rest the CSR-part
 // ---------------------------------------------------------------------------
@@ -555,7 +641,7 @@ constexpr int bcsr_waves_per_simd() {
     // (VGPR + AGPR count from the compiler's resource usage report); FP16 /
     // BF16 with 4 column groups is held one wave lower, where the fused
     // kernel fits without spilling
-    if (sizeof(TV) == 2) return VEC == 1 ? 8 : (BV == 8 ? 4 : 5);
+    if (sizeof(TV) == 2) return VEC == 1 ? (WAVE ? 7 : 8) : (BV == 8 ? (WAVE ? 3 : 4) : (WAVE ? 4 : 5));
     if (sizeof(TV) == 8) return VEC == 1 ? 4 : (BNL >= 2 ? 4 : (WAVE ? 8 : 7));
     return VEC == 1 ? (WAVE ? 7 : 6) : (BNL >= 2 ? (WAVE ? 5 : 4) : 8);
 }
@@ -572,7 +658,11 @@ void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseArgs da, uint32_t g_bcsr, uint32_t g
             // g_bcsr workgroups stride over the row-block units (one unit
             // each unless a calibrated partition caps the part's workgroups)
             const int64_t units = ba.n_rb * (int64_t)ba.n_panels;
-            if constexpr (sizeof(TV) == 2) {
+            if constexpr (sizeof(TV) == 2 && WAVE) {
+                // four units per workgroup, one per wave
+                for (int64_t u4 = (int64_t)xcd_remap(bid, g_bcsr, remap); u4 * 4 < units; u4 += g_bcsr)
+                    bcsr_wave_h<TV, BV>(ba, da, u4 * 4 + w);
+            } else if constexpr (sizeof(TV) == 2) {
                 for (int64_t unit = (int64_t)xcd_remap(bid, g_bcsr, remap); unit < units; unit += g_bcsr) {
                     bcsr_wg_h<TV, BV>(ba, da, unit, reinterpret_cast<float*>(lds_raw));
                     __syncthreads();  // the reduction buffer is reused by the next unit
@@ -722,14 +812,17 @@ int launch_cfg_w(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuer
     return HSPMM_OK;
 }
 
-// FP32 / FP64 BCSR-parts whose row blocks are all short run one wave per
-// row block; FP16 / BF16 always use the workgroup form
+// BCSR-parts whose row blocks are all short run one wave per row block
+// The FP16 / BF16 one-wave form holds 3-4 waves per SIMD; a fused launch
+// with a large CSR-part is held there too, which costs the CSR-part more
+// than the form gains (stencil FP16 with half the rows in the CSR-part:
+// 51 -> 57 us), so FP16 / BF16 take it only when the CSR-part is at most a
+// quarter of the entries (BCSR-only forward 26.5 -> 21.5 us).
 template <class TV, class TB, class TC, int VEC, int LPR, int BV, int BNL>
 int launch_cfg(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuery* q) {
-    if constexpr (sizeof(TV) != 2) {
-        if (X.rb_bcsr > 0 && X.max_rb_tiles <= kWaveMaxTiles)
-            return launch_cfg_w<TV, TB, TC, VEC, LPR, BV, BNL, true>(X, d, s, q);
-    }
+    const bool wave_ok = sizeof(TV) != 2 || 3 * X.nnz_csr <= X.nnz_bcsr;
+    if (X.rb_bcsr > 0 && X.max_rb_tiles <= kWaveMaxTiles && wave_ok)
+        return launch_cfg_w<TV, TB, TC, VEC, LPR, BV, BNL, true>(X, d, s, q);
     return launch_cfg_w<TV, TB, TC, VEC, LPR, BV, BNL, false>(X, d, s, q);
 }
 
