@@ -46,6 +46,8 @@ def parse():
                     help="structure sweep: forward GFLOP/s of the AUTO split vs CSR-only per matrix and N")
     ap.add_argument("--sweep-rows", type=int, default=100_000, help="row cap of the sweep matrices")
     ap.add_argument("--sweep-n", default="16,32,64,128,256")
+    ap.add_argument("--no-other-dtypes", action="store_true",
+                    help="skip the same step in the other compute precisions (stencil only)")
     return ap.parse_args()
 
 
@@ -249,8 +251,13 @@ def main():
     torch.cuda.synchronize()
     b_used = B.double().cpu().numpy()
     ref_c = oracle.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, b_used)
+    # the unquantised problem (end-to-end reference of the other precisions)
+    ref_c0 = ref_c if dt == "f32" and np.array_equal(b_used, b) else oracle.spmm(
+        a.m, a.k, a.row_ptr, a.col_idx, a.vals, b)
+    ref_da0 = None
     ref_db = oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, g)
     ref_da = oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, g, b_used)
+    ref_da0 = ref_da if ref_c0 is ref_c else oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, g, b)
     err = {"C": oracle.rel_err(C.double().cpu().numpy(), ref_c),
            "dB": oracle.rel_err(dB.double().cpu().numpy(), ref_db),
            "dA": oracle.rel_err(dA.double().cpu().numpy(), ref_da)}
@@ -306,6 +313,48 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": per_launch[dom]},
     }
+
+    if args.workload == "stencil" and not args.no_other_dtypes:
+        # the same step in the other precisions of the method: GFLOP/s of the
+        # AUTO and CSR-only plans and the end-to-end error of every output
+        # against the FP64 oracle (FP16/BF16: B rounded to the type, A scaled
+        # per row block, FP32 accumulation and outputs)
+        other = {}
+        for name, cdt, tol_d in (("f64", torch.float64, 1e-12), ("f16", torch.float16, 5e-3),
+                                 ("bf16", torch.bfloat16, 5e-3)):
+            Bd = torch.tensor(b, device=dev).to(cdt)
+            dCd = torch.tensor(g, device=dev) if cdt == torch.float64 else dC
+            od = torch.float64 if cdt == torch.float64 else torch.float32
+            res_d = {}
+            for split in ("auto", "csr"):
+                p = hs.Plan(a.row_ptr, a.col_idx, vals, (a.m, a.k), compute=cdt, split=split, backward=True,
+                            n_hint=n)
+                Cd = torch.empty((a.m, n), dtype=od, device=dev)
+                for _ in range(5):
+                    p.run(Bd, out=Cd)
+                    p.backward(Bd, dCd)
+                torch.cuda.synchronize()
+                steps_d = max(10, args.steps // 4)
+                t0 = time.perf_counter()
+                for _ in range(steps_d):
+                    p.run(Bd, out=Cd)
+                    p.backward(Bd, dCd)
+                torch.cuda.synchronize()
+                res_d[split] = (time.perf_counter() - t0) / steps_d
+                if split == "auto":
+                    Cd = p.run(Bd)
+                    dBd, dAd = p.backward(Bd, dCd)
+                    torch.cuda.synchronize()
+                    e = {"C": oracle.rel_err(Cd.double().cpu().numpy(), ref_c0),
+                         "dB": oracle.rel_err(dBd.double().cpu().numpy(), ref_db),
+                         "dA": oracle.rel_err(dAd.double().cpu().numpy(), ref_da0)}
+                p.close()
+            other[name] = {"value": round(flops / res_d["auto"] / 1e9, 2),
+                           "csr_only": round(flops / res_d["csr"] / 1e9, 2),
+                           "speedup_vs_csr_only": round(res_d["csr"] / res_d["auto"], 3),
+                           "error": {k: float(f"{v:.3e}") for k, v in e.items()},
+                           "error_ok": all(v <= tol_d for v in e.values()), "tol": tol_d}
+        line["other_dtypes"] = other
 
     if not args.no_cpu_baseline:
         import oracle as orc
