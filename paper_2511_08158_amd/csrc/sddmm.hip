@@ -211,10 +211,22 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
     const int nsteps = (int)ceil_div(a.n, STEP);
     const bool cached = nsteps <= NKR;
     if (cached) {
-        for (int idx = threadIdx.x; idx < 16 * NMAX; idx += 256) {
+        // 16-byte chunks (the launcher's vector path guarantees 16-byte
+        // aligned rows of dC and n a multiple of the chunk; LDS rows of
+        // NMAX + 4 elements stay 16-byte aligned)
+        constexpr int SV = VEC > 1 ? 16 / (int)sizeof(TG) : 1;
+        for (int idx = threadIdx.x * SV; idx < 16 * NMAX; idx += 256 * SV) {
             const int i = idx / NMAX, c = idx - i * NMAX;
             const int64_t row = (int64_t)rb * 16 + i;
-            lds[i * LDR + c] = (row < a.m && c < a.n) ? dC[row * a.lddc + c] : TG(0);
+            TG v[SV];
+            if (row < a.m && c < a.n) {
+                load_as<TG, SV>(dC + row * a.lddc + c, v);
+            } else {
+#pragma unroll
+                for (int e = 0; e < SV; ++e) v[e] = TG(0);
+            }
+#pragma unroll
+            for (int e = 0; e < SV; ++e) lds[i * LDR + c + e] = v[e];
         }
         __syncthreads();
     }
