@@ -6,13 +6,14 @@
 // per lane, and broadcast inside the lane group; every entry then costs one
 // coalesced VEC-wide load of a B row segment and VEC FMAs.
 //
-// BCSR-part (the outer-product kernel of Sec. 3.3, Alg. 2-3): a wavefront
-// owns one 16-row block and one column panel of C.  Each MFMA step takes
-// kc tiles of the block (a 16 x kc slab of A, packed in lane order at plan
-// time) and the kc gathered B rows, so every gathered B row serves 16 rows
-// of C.  FP64/FP32 use 16x16x4 MFMAs (kc = 4); FP16/BF16 use 16x16x32
-// MFMAs (kc = 32, the widening accumulate of Alg. 3, with FP32 sums).
-// Partial K steps are zero-filled, as Alg. 3 pairs an odd tile with zeros.
+// BCSR-part (the outer-product kernel of Sec. 3.3, Alg. 2-3): one wave, or
+// for row blocks with very many tiles one workgroup, owns one 16-row block
+// and one column panel of C.  Each MFMA step takes kc tiles of the block (a
+// 16 x kc slab of A, packed in lane order at plan time) and the kc gathered
+// B rows, so every gathered B row serves 16 rows of C.  FP64/FP32 use
+// 16x16x4 MFMAs (kc = 4); FP16/BF16 use 16x16x32 MFMAs (kc = 32, the
+// widening accumulate of Alg. 3, with FP32 sums).  Partial K steps are
+// padded with zero-valued tiles, as Alg. 3 pairs an odd tile with zeros.
 //
 // Each row of C has exactly one writer (Sec. 3.4): no atomics, and the
 // result does not depend on scheduling.
@@ -180,14 +181,7 @@ template <> struct AccOf<double> { typedef d4_t type; };
 template <class T> __device__ inline int out_row(int g, int r) { return 4 * g + r; }
 template <> __device__ inline int out_row<double>(int g, int r) { return g + 4 * r; }
 
-// One workgroup (4 waves) per (row block, column panel).  The row block's
-// K steps of 4 tiles are dealt round-robin to the 4 waves (step s -> wave
-// s % 4), so four independent gather streams run per row block; the four
-// partial 16 x PANEL tiles are then summed in a fixed order through LDS and
-// each wave stores one register row of the result.  The tile columns of up
-// to 16 rounds are fetched with one coalesced load and handed to the lanes
-// by a shuffle, so B loads never wait on an index load.
-// Operands of SB consecutive K steps of one wave.
+// K steps per load batch of the workgroup form below
 #ifndef HSPMM_STEP_BATCH
 #define HSPMM_STEP_BATCH 1
 #endif
@@ -207,6 +201,7 @@ constexpr int kStepBatch = HSPMM_STEP_BATCH;
 #ifndef HSPMM_F32_CSR_VEC8
 #define HSPMM_F32_CSR_VEC8 0
 #endif
+// Operands of SB consecutive K steps of one wave.
 template <class T, int VEC, int NL, int SB = kStepBatch>
 struct StepRegs {
     T av[SB];
