@@ -25,15 +25,29 @@ void choose_auto(const MachineModel& mm, const std::vector<int32_t>& rb_nnz,
     cls.assign(nrb, 0);
     t_csr_total = 0.0;
     t_bcsr_total = 0.0;
+    double all_csr = 0.0, all_bcsr = 0.0;
     for (size_t q = 0; q < nrb; ++q) {
         if (rb_nnz[q] == 0) continue;
         RowBlockCost c = rowblock_cost(mm, rb_nnz[q], rb_nblk[q], n, sv, sb, br, kc);
+        all_csr += c.t_csr;
+        all_bcsr += c.t_bcsr;
         if (c.t_bcsr < c.t_csr) {
             cls[q] = 1;
             t_bcsr_total += c.t_bcsr;
         } else {
             t_csr_total += c.t_csr;
         }
+    }
+    // a plan with both parts pays for them (the fused launch's register
+    // budget, a small CSR-part's split rows and their reduction launch):
+    // keep the split only if it beats the better one-part plan by more
+    // than mm.t_mixed
+    if (t_csr_total > 0.0 && t_bcsr_total > 0.0 && t_csr_total + t_bcsr_total + mm.t_mixed >= std::min(all_csr, all_bcsr)) {
+        const uint8_t to = all_bcsr <= all_csr ? 1 : 0;
+        for (size_t q = 0; q < nrb; ++q)
+            if (rb_nnz[q] != 0) cls[q] = to;
+        t_csr_total = to ? 0.0 : all_csr;
+        t_bcsr_total = to ? all_bcsr : 0.0;
     }
 }
 

@@ -21,6 +21,9 @@ struct MachineModel {
     double bw_bcsr = 6.5e12;
     double t_entry = 0.0;
     double t_blk = 31.0e-12;
+    // extra time of a plan with both parts over a one-part plan (measured:
+    // one ragged CSR row block beside a BCSR-part added 4.5 us)
+    double t_mixed = 4.0e-6;
     int cus = 256;
 };
 
