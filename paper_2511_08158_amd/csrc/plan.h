@@ -36,6 +36,7 @@ struct SubPlan {
     DevBuf blk_mask;      // uint16 [nblk_pad]: bit i set when row i of the tile holds an entry
     std::vector<int32_t> h_bcsr_rb, h_blk_ptr, h_blk_cnt;
     int64_t max_rb_tiles = 0;  // most tiles in one row block of the BCSR-part
+    int32_t max_long_cnt = 0;  // most segments of one split CSR row
 
     DevBuf scale;                 // double [nrb] (scaled sub-plans only)
 

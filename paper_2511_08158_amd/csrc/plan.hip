@@ -562,6 +562,7 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
     X.n_vrows = (int64_t)vs.size();
     X.n_long = (int64_t)lrow.size();
     X.n_partials = nparts;
+    X.max_long_cnt = lcnt.empty() ? 0 : *std::max_element(lcnt.begin(), lcnt.end());
 
     HSPMM_TRY(upload(al, X.csr_rows, rows, s));
     HSPMM_TRY(upload(al, X.csr_ptr, cptr, s));

@@ -693,22 +693,91 @@ void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseArgs da, uint32_t g_bcsr, uint32_t g
     }
 }
 
-template <class TC, class Acc>
-__global__ __launch_bounds__(256) void k_long_reduce(const int32_t* __restrict__ long_row,
-                                                     const int32_t* __restrict__ long_first,
-                                                     const int32_t* __restrict__ long_cnt, int64_t n_long,
-                                                     const Acc* __restrict__ ws, TC* __restrict__ C,
-                                                     int64_t ldc, int64_t n, const double* __restrict__ scale) {
-    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (w >= n_long) return;
+// Sum of the partial rows of split CSR rows.  A workgroup takes one long
+// row and a chunk of up to 64*V columns; lanes form groups of L lanes (V
+// columns each) that cover the chunk, and group g adds the row's partials
+// g, g + NG, g + 2 NG, ... (NG = BT / L groups, RU loads in flight each).
+// The group sums are then added in group order through LDS: the order is
+// fixed by (cnt, L, BT), so repeated runs give identical results.  Rows cut
+// into hundreds of segments are summed by many waves at once instead of one
+// lane walking every partial in turn.
+template <class TC, class Acc, int V, int BT>
+__global__ __launch_bounds__(BT) void k_long_reduce(const int32_t* __restrict__ long_row,
+                                                    const int32_t* __restrict__ long_first,
+                                                    const int32_t* __restrict__ long_cnt,
+                                                    const Acc* __restrict__ ws, TC* __restrict__ C,
+                                                    int64_t ldc, int64_t n, int L,
+                                                    const double* __restrict__ scale) {
+    constexpr int RU = 4;
+    __shared__ Acc red[BT * V];
+    const int t = threadIdx.x;
+    const int NG = BT / L, g = t / L, gl = t % L;
+    const int64_t col = (int64_t)blockIdx.y * 64 * V + (int64_t)gl * V;
+    const bool colok = col < n;
+    const int64_t w = blockIdx.x;
     const int row = long_row[w], first = long_first[w], cnt = long_cnt[w];
-    const Acc s = scale ? (Acc)scale[row >> 4] : Acc(1);
-    for (int64_t c = lane; c < n; c += 64) {
-        Acc sum = Acc(0);
-        for (int q = 0; q < cnt; ++q) sum += ws[(int64_t)(first + q) * n + c];
-        C[(int64_t)row * ldc + c] = (TC)(sum * s);
+    Acc acc[RU][V];
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[u][v] = Acc(0);
+    if (colok) {
+        for (int q0 = g; q0 < cnt; q0 += NG * RU) {
+            Acc x[RU][V];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int q = q0 + u * NG;
+                if (q < cnt) {
+                    load_vec<Acc, V>(ws + (int64_t)(first + q) * n + col, x[u]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) x[u][v] = Acc(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[u][v] += x[u][v];
+        }
     }
+#pragma unroll
+    for (int v = 0; v < V; ++v) red[t * V + v] = ((acc[0][v] + acc[1][v]) + acc[2][v]) + acc[3][v];
+    __syncthreads();
+    if (g == 0 && colok) {
+        Acc sum[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) sum[v] = red[gl * V + v];
+        for (int h = 1; h < NG; ++h)
+#pragma unroll
+            for (int v = 0; v < V; ++v) sum[v] += red[(h * L + gl) * V + v];
+        const Acc sc = scale ? (Acc)scale[row >> 4] : Acc(1);
+#pragma unroll
+        for (int v = 0; v < V; ++v) C[(int64_t)row * ldc + col + v] = (TC)(sum[v] * sc);
+    }
+}
+
+// Launch of the reduction above: V columns per lane when the partial rows
+// allow 16-byte loads, and 1024 threads when some row has many partials.
+template <class TC, class Acc>
+void launch_long_reduce(const SubPlan& X, const DenseArgs& d, hipStream_t s) {
+    constexpr int VW = 16 / (int)sizeof(Acc);
+    const bool vec = d.n % VW == 0 && (uintptr_t)d.ws % 16 == 0;
+    const int V = vec ? VW : 1;
+    int L = 1;
+    while (L < 64 && (int64_t)L * V < d.n) L <<= 1;
+    const dim3 grid((unsigned)X.n_long, (unsigned)ceil_div(d.n, (int64_t)64 * V));
+    const bool big = X.max_long_cnt >= 64;
+    const Acc* ws = static_cast<const Acc*>(d.ws);
+    TC* C = static_cast<TC*>(d.C);
+#define HSPMM_LR(VV, BB)                                                                                     \
+    hipLaunchKernelGGL((k_long_reduce<TC, Acc, VV, BB>), grid, dim3(BB), 0, s, X.long_row.as<int32_t>(),   \
+                       X.long_first.as<int32_t>(), X.long_cnt.as<int32_t>(), ws, C, d.ldc, d.n, L, d.scale)
+    if (vec) {
+        if (big) HSPMM_LR(VW, 1024); else HSPMM_LR(VW, 256);
+    } else {
+        if (big) HSPMM_LR(1, 1024); else HSPMM_LR(1, 256);
+    }
+#undef HSPMM_LR
 }
 
 inline uint32_t pad8(int64_t g) { return (uint32_t)(ceil_div(g, 8) * 8); }
@@ -798,10 +867,7 @@ int launch_cfg_w(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuer
     HIP_LAUNCH_CHECK();
     if (X.n_long > 0) {
         typedef typename Elem<TB>::acc_t acc_t;
-        const unsigned blocks = (unsigned)ceil_div(X.n_long, 4);
-        hipLaunchKernelGGL((k_long_reduce<TC, acc_t>), dim3(blocks), dim3(256), 0, s, X.long_row.as<int32_t>(),
-                           X.long_first.as<int32_t>(), X.long_cnt.as<int32_t>(), X.n_long,
-                           static_cast<const acc_t*>(d.ws), static_cast<TC*>(d.C), d.ldc, d.n, d.scale);
+        launch_long_reduce<TC, acc_t>(X, d, s);
         HIP_LAUNCH_CHECK();
     }
     return HSPMM_OK;

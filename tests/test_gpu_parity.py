@@ -127,6 +127,31 @@ def test_long_rows_are_split_deterministically():
     assert oracle.rel_err(C1, oracle_forward(a, B)) <= 1e-5
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16])
+@pytest.mark.parametrize("n", [5, 64, 300])
+@pytest.mark.parametrize("longest", [1500, 17000])
+def test_long_row_reduce_forms(dtype, n, longest):
+    """Partial rows of split rows are summed by one workgroup per (row,
+    column chunk): rows of 4 and 47 (small workgroup) or 532 segments (large
+    workgroup), n odd (one column per lane), 64 (one chunk) and 300 (two or
+    three chunks of 16-byte loads); parity and bitwise-repeatable results."""
+    print(f"long-row reduce dtype={dtype} n={n} longest={longest}", flush=True)
+    g = np.random.default_rng(11)
+    m, k = 96, 20000
+    lens = np.full(m, 3)
+    lens[[0, 17, 95]] = [100, 1500, longest]
+    rows = np.repeat(np.arange(m), lens)
+    cols = np.concatenate([np.sort(g.choice(k, l, replace=False)) for l in lens])
+    a = gen.csr_from_coo(m, k, rows, cols, g.standard_normal(rows.size))
+    B = g.standard_normal((k, n))
+    plan = make_plan(hs, a, dtype, "csr")
+    assert plan.info()["long_rows"] == 3
+    C1 = _run(plan, B, dtype)
+    C2 = _run(plan, B, dtype)
+    assert np.array_equal(C1, C2)
+    assert oracle.rel_err(C1, oracle_forward(a, B)) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_wide_row_blocks_forward(dtype):
     """FP32/FP64 BCSR-parts run one wave per row block when every row block
