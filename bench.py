@@ -46,6 +46,9 @@ def parse():
                     help="structure sweep: forward GFLOP/s of the AUTO split vs CSR-only per matrix and N")
     ap.add_argument("--sweep-rows", type=int, default=100_000, help="row cap of the sweep matrices")
     ap.add_argument("--sweep-n", default="16,32,64,128,256")
+    ap.add_argument("--gcn-train", action="store_true",
+                    help="time a two-layer graph-convolution training loop on the 232,965-node graph")
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--no-other-dtypes", action="store_true",
                     help="skip the same step in the other compute precisions (stencil only)")
     return ap.parse_args()
@@ -123,6 +126,111 @@ def sweep(args):
                                         "max_err": max(r.get("err", 0.0) for r in rows)}}), flush=True)
 
 
+def gcn_train(args):
+    """Two-layer graph convolution trained on the synthetic 232,965-node
+    graph: H = relu(A (X W1)), logits = A (H W2), cross entropy on seeded
+    labels, plain SGD on W1 and W2.  The sparse products run in the library
+    through its autograd function (A is constant, so its backward is the
+    transposed product alone); the dense products, activation and loss are
+    PyTorch.  Reports the epoch time, the sparse products' share of it, the
+    plan time against 100 epochs (the paper amortises format conversion over
+    training), and the first step's weight gradients against an FP64 scipy
+    evaluation of the same network."""
+    import numpy as np
+    import torch
+    import torch.nn.functional as F
+
+    import gen
+    import paper_2511_08158_amd as hs
+
+    dev = torch.device("cuda:0")
+    a, x = gen.config4()
+    hidden, classes = x.shape[1], 16
+    g = np.random.default_rng([0, 5])
+    w1 = g.standard_normal((x.shape[1], hidden)) / np.sqrt(x.shape[1])
+    w2 = g.standard_normal((hidden, classes)) / np.sqrt(hidden)
+    lab = g.integers(0, classes, a.m)
+    X = torch.tensor(x, device=dev, dtype=torch.float32)
+    labels = torch.tensor(lab, device=dev)
+    W1 = torch.tensor(w1, device=dev, dtype=torch.float32, requires_grad=True)
+    W2 = torch.tensor(w2, device=dev, dtype=torch.float32, requires_grad=True)
+    vals = torch.tensor(a.vals, device=dev, dtype=torch.float32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = hs.Plan(a.row_ptr, a.col_idx, vals, (a.m, a.k), compute=torch.float32, backward=True, n_hint=hidden)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    opt = torch.optim.SGD([W1, W2], lr=0.5)
+
+    def forward():
+        H = torch.relu(hs.spmm(plan, vals, X @ W1))
+        return F.cross_entropy(hs.spmm(plan, vals, H @ W2), labels)
+
+    # first step's gradients against FP64 scipy
+    loss0 = forward()
+    loss0.backward()
+    gw1, gw2 = W1.grad.double().cpu().numpy(), W2.grad.double().cpu().numpy()
+    A = a.to_scipy().tocsr()
+    z1 = A @ (x @ w1)
+    h = np.maximum(z1, 0.0)
+    logits = A @ (h @ w2)
+    pr = np.exp(logits - logits.max(axis=1, keepdims=True))
+    pr /= pr.sum(axis=1, keepdims=True)
+    ref_loss = float(-np.mean(np.log(pr[np.arange(a.m), lab])))
+    dl = pr
+    dl[np.arange(a.m), lab] -= 1.0
+    dl /= a.m
+    dhw2 = A.T @ dl
+    rw2 = h.T @ dhw2
+    dz1 = (dhw2 @ w2.T) * (z1 > 0)
+    rw1 = x.T @ (A.T @ dz1)
+    rel = lambda u, v: float(np.linalg.norm(u - v) / np.linalg.norm(v))
+
+    def epoch():
+        opt.zero_grad(set_to_none=True)
+        loss = forward()
+        loss.backward()
+        opt.step()
+        return loss
+
+    for _ in range(3):
+        epoch()
+    torch.cuda.synchronize()
+    losses = []
+    t0 = time.perf_counter()
+    for _ in range(args.epochs):
+        losses.append(epoch())
+    torch.cuda.synchronize()
+    epoch_ms = (time.perf_counter() - t0) / args.epochs * 1e3
+    # the sparse products of one epoch alone: two forward products (n = 128,
+    # 16) and their two transposed products
+    B1 = torch.randn(a.k, hidden, device=dev)
+    B2 = torch.randn(a.k, classes, device=dev)
+    D1 = torch.randn(a.m, hidden, device=dev)
+    D2 = torch.randn(a.m, classes, device=dev)
+    reps = 10
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.run(B1)
+        plan.run(B2)
+        plan.backward(B2, D2, need_dA=False)
+        plan.backward(B1, D1, need_dA=False)
+    torch.cuda.synchronize()
+    sp_ms = (time.perf_counter() - t0) / reps * 1e3
+    line = {"gcn_train": {
+        "nodes": a.m, "nnz": a.nnz, "features": x.shape[1], "hidden": hidden, "classes": classes,
+        "epochs_timed": args.epochs, "epoch_ms": round(epoch_ms, 3),
+        "sparse_ms_per_epoch": round(sp_ms, 3), "sparse_share": round(sp_ms / epoch_ms, 3),
+        "plan_ms": round(plan_ms, 1), "plan_share_100_epochs": round(plan_ms / (plan_ms + 100 * epoch_ms), 4),
+        "split": {k: plan.info()[k] for k in ("rows_csr", "rb_bcsr")},
+        "loss_first": round(float(loss0), 5), "loss_first_fp64": round(ref_loss, 5),
+        "loss_last": round(float(losses[-1]), 5),
+        "grad_rel_err_first_step": {"W1": float(f"{rel(gw1, rw1):.2e}"), "W2": float(f"{rel(gw2, rw2):.2e}")},
+        "data": "synthetic"}}
+    print(json.dumps(line), flush=True)
+
+
 def copy_probe():
     """A plain copy kernel of known size: 1 GiB read + 1 GiB written per launch."""
     import torch
@@ -171,6 +279,9 @@ def main():
         return
     if args.sweep:
         sweep(args)
+        return
+    if args.gcn_train:
+        gcn_train(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -235,13 +346,37 @@ def main():
             out[name] = e0.elapsed_time(e1) / reps * 1e3  # us
         return out
 
+    flush_buf = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+
+    def step_percentiles(plan, reps, cold):
+        """Per-step durations (HIP events around each step on the launch
+        stream); cold: a 1 GiB fill between steps, outside the events, evicts
+        the inputs from L2 and the 256 MB MALL."""
+        C = torch.empty((a.m, n), dtype=torch.float32, device=dev)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for i in range(reps + 2):
+            if cold:
+                flush_buf.fill_(float(i))
+            if i >= 2:
+                ev[i - 2][0].record(stream)
+            plan.run(B, out=C)
+            plan.backward(B, dC)
+            if i >= 2:
+                ev[i - 2][1].record(stream)
+        torch.cuda.synchronize()
+        us = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev])
+        return {q: float(np.percentile(us, p)) for q, p in (("p10", 10), ("p50", 50), ("p90", 90))}
+
     results = {}
     for split in ("auto", "csr"):
         plan, plan_ms = make(split)
         t = time_steps(plan, args.steps, args.warmup)
         kt = time_kernels(plan, max(10, args.steps))
+        reps_p = max(10, min(100, args.steps))
         results[split] = {"plan": plan, "t": t, "plan_ms": plan_ms, "kernels_us": kt,
-                          "info": plan.info()}
+                          "info": plan.info(), "warm": step_percentiles(plan, reps_p, False),
+                          "cold": step_percentiles(plan, reps_p, True)}
+    del flush_buf
 
     # errors of the hybrid outputs against the FP64 oracle
     import oracle
@@ -304,6 +439,12 @@ def main():
         "csr_only": {"value": round(flops / t_c / 1e9, 2), "ms_per_step": round(t_c * 1e3, 5),
                      "kernels_us": {k: round(v, 2) for k, v in results["csr"]["kernels_us"].items()}},
         "speedup_vs_csr_only": round(t_c / t_h, 3),
+        "step_us_percentiles": {
+            mode: {"auto": {k: round(v, 2) for k, v in results["auto"][mode].items()},
+                   "csr_only": {k: round(v, 2) for k, v in results["csr"][mode].items()},
+                   "gflops_p50": round(flops / (results["auto"][mode]["p50"] * 1e-6) / 1e9, 1),
+                   "speedup_vs_csr_only_p50": round(results["csr"][mode]["p50"] / results["auto"][mode]["p50"], 3)}
+            for mode in ("warm", "cold")},
         "error": {k: float(f"{v:.3e}") for k, v in err.items()},
         "error_ok": all(v <= tol for v in err.values()),
         "kernels_us": {k: round(v, 2) for k, v in kt.items()},
