@@ -33,7 +33,16 @@ struct SubPlan {
     // BCSR-part (Alg. 1 step 2): B_r x 1 tiles, values packed in MFMA lane order
     int64_t rb_bcsr = 0, nblk = 0, nblk_pad = 0, nnz_bcsr = 0;
     DevBuf bcsr_rb, blk_ptr, blk_cnt, blk_col, blk_val, blk_src;
-    DevBuf blk_mask;      // uint16 [nblk_pad]: bit i set when row i of the tile holds an entry
+    // SDDMM destinations (A only), per chunk of 16 consecutive tiles of a
+    // BCSR row block, the SDDMM's unit of work.  For row R of the block at
+    // position p (R in the order in which the MFMA output holds rows:
+    // lane group p / 4, register p % 4): bit t of chunk_mask[c][p] is set
+    // when tile t of the chunk holds an entry of row R, and chunk_base[c][p]
+    // is the canonical index of row R's first entry at or after the chunk
+    DevBuf chunk_ptr;     // int32 [rb_bcsr + 1]: first chunk of each BCSR row block
+    DevBuf chunk_base;    // int32 [nchunks][16]
+    DevBuf chunk_mask;    // uint16 [nchunks][16]
+    int64_t nchunks = 0;
     std::vector<int32_t> h_bcsr_rb, h_blk_ptr, h_blk_cnt;
     int64_t max_rb_tiles = 0;  // most tiles in one row block of the BCSR-part
     int32_t max_long_cnt = 0;  // most segments of one split CSR row

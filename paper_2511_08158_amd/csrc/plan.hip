@@ -188,6 +188,34 @@ __global__ void k_build_mask(const int32_t* __restrict__ blk_src, int64_t nblk_p
     }
 }
 
+// SDDMM chunk tables: one thread per (row block, row) walks the row block's
+// chunks of 16 tiles in order, keeping the running canonical index of the
+// row's next entry (tiles are sorted by column, as are a row's entries)
+__global__ void k_build_chunk_meta(const int32_t* __restrict__ bcsr_rb, const int32_t* __restrict__ blk_ptr,
+                                   const int32_t* __restrict__ blk_cnt, const uint16_t* __restrict__ blk_mask,
+                                   const int32_t* __restrict__ chunk_ptr, const int32_t* __restrict__ canon_rp,
+                                   int64_t m, int64_t n_rb, bool interleaved, int32_t* __restrict__ chunk_base,
+                                   uint16_t* __restrict__ chunk_mask) {
+    GRID_STRIDE(x, n_rb * 16) {
+        const int64_t slot = x >> 4;
+        const int R = (int)(x & 15);
+        const int64_t row = (int64_t)bcsr_rb[slot] * 16 + R;
+        const int b0 = blk_ptr[slot], cnt = blk_cnt[slot];
+        const int64_t c0 = chunk_ptr[slot];
+        // position of row R in the MFMA output: FP64 holds rows g + 4r in
+        // lane group g, register r; the other types rows 4g + r
+        const int pos = interleaved ? 4 * (R & 3) + (R >> 2) : R;
+        int32_t run = row < m ? canon_rp[row] : 0;
+        for (int c = 0; 16 * c < cnt; ++c) {
+            uint32_t mk = 0;
+            for (int t = 0; t < 16 && 16 * c + t < cnt; ++t) mk |= ((blk_mask[b0 + 16 * c + t] >> R) & 1u) << t;
+            chunk_mask[(c0 + c) * 16 + pos] = (uint16_t)mk;
+            chunk_base[(c0 + c) * 16 + pos] = run;
+            run += __popc(mk);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // values
 // ---------------------------------------------------------------------------
@@ -590,6 +618,7 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
     std::vector<int32_t> rb_slot(nrb, -1);
     int64_t pad_acc = 0;
     X.nblk = 0;
+    X.nchunks = 0;
     X.max_rb_tiles = 0;
     X.nnz_bcsr = 0;
     for (int64_t q = 0; q < nrb; ++q) {
@@ -621,10 +650,27 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
                            hd.as<int32_t>(), hx.as<int32_t>(), row_of, col, src, rp, d_slot.as<int32_t>(),
                            X.blk_ptr.as<int32_t>(), n, half, X.blk_col.as<int32_t>(), X.blk_src.as<int32_t>());
         HIP_LAUNCH_CHECK();
-        HSPMM_TRY(al.alloc(X.blk_mask, (size_t)X.nblk_pad * 2));
-        hipLaunchKernelGGL(k_build_mask, dim3(grid_for(X.nblk_pad)), dim3(kThreads), 0, s, X.blk_src.as<int32_t>(),
-                           X.nblk_pad, half, static_cast<uint16_t*>(X.blk_mask.ptr));
-        HIP_LAUNCH_CHECK();
+        if (&X == &p.A) {
+            DevBuf mask;
+            HSPMM_TRY(al.alloc(mask, (size_t)X.nblk_pad * 2));
+            hipLaunchKernelGGL(k_build_mask, dim3(grid_for(X.nblk_pad)), dim3(kThreads), 0, s,
+                               X.blk_src.as<int32_t>(), X.nblk_pad, half, static_cast<uint16_t*>(mask.ptr));
+            HIP_LAUNCH_CHECK();
+            std::vector<int32_t> cptr(1, 0);
+            for (int32_t c : X.h_blk_cnt) cptr.push_back(cptr.back() + (int32_t)ceil_div(c, 16));
+            X.nchunks = cptr.back();
+            HSPMM_TRY(upload(al, X.chunk_ptr, cptr, s));
+            HSPMM_TRY(al.alloc(X.chunk_base, (size_t)X.nchunks * 16 * 4));
+            HSPMM_TRY(al.alloc(X.chunk_mask, (size_t)X.nchunks * 16 * 2));
+            hipLaunchKernelGGL(k_build_chunk_meta, dim3(grid_for(X.rb_bcsr * 16)), dim3(kThreads), 0, s,
+                               X.bcsr_rb.as<int32_t>(), X.blk_ptr.as<int32_t>(), X.blk_cnt.as<int32_t>(),
+                               static_cast<const uint16_t*>(mask.ptr), X.chunk_ptr.as<int32_t>(), rp, X.m,
+                               X.rb_bcsr, X.ct == HSPMM_F64, X.chunk_base.as<int32_t>(),
+                               static_cast<uint16_t*>(X.chunk_mask.ptr));
+            HIP_LAUNCH_CHECK();
+            HIP_TRY(hipStreamSynchronize(s));
+            al.free(mask);
+        }
         HIP_TRY(hipStreamSynchronize(s));
         al.free(d_slot);
     }
@@ -866,7 +912,8 @@ int64_t SubPlan::bytes() const {
     return (int64_t)(csr_rows.bytes + csr_ptr.bytes + csr_col.bytes + csr_val.bytes + csr_src.bytes +
                      vr_start.bytes + vr_end.bytes + vr_out.bytes + vr_row.bytes + long_row.bytes + long_first.bytes +
                      long_cnt.bytes + bcsr_rb.bytes + blk_ptr.bytes + blk_cnt.bytes + blk_col.bytes +
-                     blk_val.bytes + blk_src.bytes + scale.bytes);
+                     blk_val.bytes + blk_src.bytes + chunk_ptr.bytes + chunk_base.bytes + chunk_mask.bytes +
+                     scale.bytes);
 }
 
 }  // namespace hspmm

@@ -25,8 +25,9 @@ struct SddArgs {
     const int32_t* blk_ptr;
     const int32_t* blk_cnt;
     const int32_t* blk_col;
-    const uint16_t* blk_mask;  // rows of each tile that hold an entry
-    const int32_t* canon_rp;   // canonical row pointer of A
+    const int32_t* chunk_ptr;    // first chunk of 16 tiles of each row block
+    const int32_t* chunk_base;   // [chunk][16] canonical index of each row's first entry in the chunk
+    const uint16_t* chunk_mask;  // [chunk][16] tiles of the chunk that hold an entry of each row
     int64_t n_rb;
     // dense operands
     const void* B;
@@ -151,38 +152,6 @@ template <> struct AccOf<float> { typedef f4_t type; };
 template <> struct AccOf<double> { typedef d4_t type; };
 template <class T> __host__ __device__ constexpr int out_row(int g, int r) { return 4 * g + r; }
 template <> __host__ __device__ constexpr int out_row<double>(int g, int r) { return g + 4 * r; }
-// inverse of out_row: the lane group and register that hold row R
-template <class T> __host__ __device__ constexpr int row_group(int R) { return R >> 2; }
-template <> __host__ __device__ constexpr int row_group<double>(int R) { return R & 3; }
-template <class T> __host__ __device__ constexpr int row_reg(int R) { return R & 3; }
-template <> __host__ __device__ constexpr int row_reg<double>(int R) { return R >> 2; }
-
-// Destinations of a chunk's results.  The tiles of a row block are sorted by
-// column, and so are the entries of each canonical row, so the entry of row
-// R in tile t sits at canon_rp[R] + (number of earlier tiles of the row
-// block that hold row R).  A round is the 64 consecutive tiles whose four
-// chunks go to the four waves; lane l holds the occupancy mask of tile l of
-// the round, and one ballot per row gives that row's presence in all 64.
-// Each wave walks every round up to its own chunk and keeps the running
-// count of its lanes' four rows: 2 bytes of mask per tile instead of 16
-// stored destinations.
-template <class TG>
-__device__ inline void chunk_dst(uint32_t mt, int w, int j, int q, const int32_t (&rbase)[4], int32_t (&run)[4],
-                                 int32_t (&dst)[4]) {
-    const uint32_t below = (1u << j) - 1u;
-#pragma unroll
-    for (int R = 0; R < 16; ++R) {
-        const uint64_t b = __ballot((mt >> R) & 1u);
-        const uint32_t bits = (uint32_t)(b >> (16 * w)) & 0xffffu;
-        const int before = __popcll(b & ((1ull << (16 * w)) - 1ull));
-        const int r = row_reg<TG>(R);
-        // selects, not branches: the lanes of group row_group(R) own row R
-        const bool mine = q == row_group<TG>(R);
-        const int d = ((bits >> j) & 1u) ? rbase[r] + run[r] + before + __popc(bits & below) : -1;
-        dst[r] = mine ? d : dst[r];
-        run[r] += mine ? __popcll(b) : 0;
-    }
-}
 
 // One workgroup per row block.  K of the MFMA runs over the n columns:
 // lane (i, q) supplies columns kbase + q*VEC + v of dC row i and of B row j,
@@ -240,26 +209,13 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
     // occupancy, and no slower than 2
     constexpr int GB = (HSPMM_SDD_GATHER > 0 && HSPMM_SDD_GATHER < NKR) ? HSPMM_SDD_GATHER : NKR;
     static_assert(NKR % GB == 0, "gather batch must divide the cached steps");
-    // canonical position of the first entry of each of this lane's rows, and
-    // the entries of those rows in the tiles walked so far
-    int32_t rbase[4], run[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t row = (int64_t)rb * 16 + out_row<TG>(q, r);
-        rbase[r] = a.canon_rp[row < a.m ? row : a.m];
-        run[r] = 0;
-    }
+    // this lane's rows out_row(q, r) sit at positions 4q + r of the chunk tables
+    const int64_t chunk0 = a.chunk_ptr[slot];
+    const uint32_t below = (1u << j) - 1u;
     for (int it0 = 0; 16 * w + 64 * it0 < cnt; it0 += 4) {
         // tile columns of this wave's next four chunks: lane l -> chunk it0 + l/16
         const int pre = 16 * w + 64 * (it0 + (lane >> 4)) + j;
         const int colreg = pre < cnt ? a.blk_col[b0 + pre] : 0;
-        // occupancy masks of the next four rounds: lane l -> tile l of the round
-        uint32_t mk[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int t = 64 * (it0 + k) + lane;
-            mk[k] = t < cnt ? a.blk_mask[b0 + t] : 0u;
-        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int it = it0 + k;
@@ -267,8 +223,11 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
             if (c0 >= cnt) break;
             const int bc = __shfl(colreg, (16 * k + j) & 63, 64);
             const bool bok = c0 + j < cnt;
-            int32_t dst[4] = {-1, -1, -1, -1};
-            chunk_dst<TG>(mk[k], w, j, q, rbase, run, dst);
+            // destinations: the first canonical index of each of the lane's
+            // four rows in this chunk, and which tiles of the chunk hold them
+            const int64_t ci = chunk0 + (c0 >> 4);
+            const int4 cb = *reinterpret_cast<const int4*>(a.chunk_base + ci * 16 + 4 * q);
+            const uint2 cm = *reinterpret_cast<const uint2*>(a.chunk_mask + ci * 16 + 4 * q);
             acc_v acc = acc_v{0, 0, 0, 0};
             if (cached) {
                 // the gathers of GB steps first, then their products.  The
@@ -312,10 +271,13 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
                     for (int v = 0; v < VEC; ++v) acc = mfma4(gv[v], bv[v], acc);
                 }
             }
-            // lane (j, q) holds rows out_row(q, r) of tile c0 + j
+            // lane (j, q) holds rows out_row(q, r) of tile c0 + j; the row's
+            // entries in the chunk are consecutive in canonical order
+            const int32_t base[4] = {cb.x, cb.y, cb.z, cb.w};
+            const uint32_t bits[4] = {cm.x & 0xffffu, cm.x >> 16, cm.y & 0xffffu, cm.y >> 16};
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                if (dst[r] >= 0) dA[dst[r]] = acc[r];
+                if ((bits[r] >> j) & 1u) dA[base[r] + __popc(bits[r] & below)] = acc[r];
         }
     }
 }
@@ -415,8 +377,8 @@ int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC,
     } else {
         SddArgs a{X.vr_start.as<int32_t>(), X.vr_end.as<int32_t>(), X.vr_row.as<int32_t>(), X.csr_col.as<int32_t>(),
                   X.csr_src.as<int32_t>(), X.n_vrows, X.bcsr_rb.as<int32_t>(), X.blk_ptr.as<int32_t>(),
-                  X.blk_cnt.as<int32_t>(), X.blk_col.as<int32_t>(), static_cast<const uint16_t*>(X.blk_mask.ptr),
-                  p.canon_rp.as<int32_t>(), X.rb_bcsr, B, ldb, dC, lddc, n, X.m, target};
+                  X.blk_cnt.as<int32_t>(), X.blk_col.as<int32_t>(), X.chunk_ptr.as<int32_t>(),
+                  X.chunk_base.as<int32_t>(), static_cast<const uint16_t*>(X.chunk_mask.ptr), X.rb_bcsr, B, ldb, dC, lddc, n, X.m, target};
         const size_t eb = dtype_size(X.ct);
         const int rc = [&]() -> int {
             switch (X.ct) {
