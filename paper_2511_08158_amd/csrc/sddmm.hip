@@ -201,12 +201,13 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
     }
     const TG* __restrict__ gl_row = lds + j * LDR + q * VEC;
 #ifndef HSPMM_SDD_GATHER
-#define HSPMM_SDD_GATHER 4
+#define HSPMM_SDD_GATHER 8
 #endif
-    // steps whose gathers are in flight together: 4 (a lane's 4 x 16-byte
-    // gathers) measured faster than all NKR at once (FP32 -9%, FP16 -17%,
-    // FP64 -9% on the block stencil), the smaller register set buying
-    // occupancy, and no slower than 2
+    // steps whose gathers are in flight together: 8 (a lane's 8 x 16-byte
+    // gathers, every step of n = 128 FP32) at 52-56 registers; on the block
+    // stencil 2-5 % faster than 4 (FP32 37.1 against 37.6 us, FP16 34.9
+    // against 35.7) and 2 slower again.  With per-call destination ballots
+    // the kernel needed 68 registers and 4 won by 9-17 %.
     constexpr int GB = (HSPMM_SDD_GATHER > 0 && HSPMM_SDD_GATHER < NKR) ? HSPMM_SDD_GATHER : NKR;
     static_assert(NKR % GB == 0, "gather batch must divide the cached steps");
     // this lane's rows out_row(q, r) sit at positions 4q + r of the chunk tables
@@ -282,6 +283,100 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
     }
 }
 
+// FP16 row blocks on 16x16x32 MFMAs (K = 32 columns of n per step).  The
+// 16 x n slab of dC is staged in LDS as FP16 after an exact power-of-two
+// scale s that puts its largest magnitude in [2^14, 2^15) (no overflow, and
+// the FP16 normal range below it is kept), so the only change to dC is one
+// FP16 rounding per element, as for B; products accumulate in FP32 and the
+// results are multiplied back by s.  Lane (i, q) supplies dC row i and B
+// row j of the step's columns 8q .. 8q + 7: one 16-byte LDS read and one
+// 16-byte gather per step.  The launcher guarantees n <= 32 NKH, n a
+// multiple of 8, 16-byte aligned rows of B and dC.
+template <int NKH>
+__device__ void sdd_bcsr_wg_h(const SddArgs& a, int64_t slot, unsigned char* smem) {
+    if (slot >= a.n_rb) return;  // uniform over the workgroup
+    constexpr int NMAX = 32 * NKH;
+    constexpr int LDR = NMAX + 8;  // halfs per LDS row: rows stay 16-byte aligned
+    constexpr int NV = NMAX / 64;  // float4 of the slab per thread
+    half_t* lds = reinterpret_cast<half_t*>(smem);
+    float* red = reinterpret_cast<float*>(smem + 16 * LDR * sizeof(half_t));
+    const int lane = threadIdx.x & 63, w = wave_id(), j = lane & 15, q = lane >> 4;
+    const int rb = a.rb[slot];
+    const int b0 = a.blk_ptr[slot];
+    const int cnt = a.blk_cnt[slot];
+    const half_t* __restrict__ B = static_cast<const half_t*>(a.B);
+    const float* __restrict__ dC = static_cast<const float*>(a.dC);
+    float* __restrict__ dA = static_cast<float*>(a.dA);
+    f4_t x[NV];
+    float mx = 0.f;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int idx = (threadIdx.x + 256 * v) * 4;
+        const int i = idx / NMAX, c = idx - i * NMAX;
+        const int64_t row = (int64_t)rb * 16 + i;
+        x[v] = (row < a.m && c < a.n) ? *reinterpret_cast<const f4_t*>(dC + row * a.lddc + c) : f4_t{0.f, 0.f, 0.f, 0.f};
+        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x[v][0]), fabsf(x[v][1])), fmaxf(fabsf(x[v][2]), fabsf(x[v][3]))));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) red[w] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    // mx in [2^(e-1), 2^e); a zero or non-finite slab is left unscaled
+    int e = 0;
+    (void)frexpf(mx, &e);
+    const bool scl = mx > 0.f && mx <= 3.4e38f;
+    const float s = scl ? ldexpf(1.f, e - 15) : 1.f;
+    const float inv = scl ? ldexpf(1.f, 15 - e) : 1.f;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int idx = (threadIdx.x + 256 * v) * 4;
+        const int i = idx / NMAX, c = idx - i * NMAX;
+        typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+        h4_t hv;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) hv[t] = (half_t)(x[v][t] * inv);
+        *reinterpret_cast<h4_t*>(lds + i * LDR + c) = hv;
+    }
+    __syncthreads();
+    const half_t* __restrict__ arow = lds + j * LDR + q * 8;
+    const int64_t chunk0 = a.chunk_ptr[slot];
+    const uint32_t below = (1u << j) - 1u;
+    for (int it0 = 0; 16 * w + 64 * it0 < cnt; it0 += 4) {
+        // tile columns of this wave's next four chunks: lane l -> chunk it0 + l/16
+        const int pre = 16 * w + 64 * (it0 + (lane >> 4)) + j;
+        const int colreg = pre < cnt ? a.blk_col[b0 + pre] : 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c0 = 16 * w + 64 * (it0 + k);
+            if (c0 >= cnt) break;
+            const int bc = __shfl(colreg, (16 * k + j) & 63, 64);
+            const int64_t ci = chunk0 + (c0 >> 4);
+            const int4 cb = *reinterpret_cast<const int4*>(a.chunk_base + ci * 16 + 4 * q);
+            const uint2 cm = *reinterpret_cast<const uint2*>(a.chunk_mask + ci * 16 + 4 * q);
+            // unconditional gathers: a tile past the row block's end reads
+            // row 0 of B, a step past n reads column 0 against zeros in LDS
+            h8_t bv[NKH];
+#pragma unroll
+            for (int t = 0; t < NKH; ++t) {
+                const int64_t c = (int64_t)t * 32 + q * 8;
+                bv[t] = *reinterpret_cast<const h8_t*>(B + (int64_t)bc * a.ldb + (c < a.n ? c : 0));
+            }
+            f4_t acc = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < NKH; ++t) {
+                const h8_t av = *reinterpret_cast<const h8_t*>(arow + t * 32);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv[t], acc, 0, 0, 0);
+            }
+            const int32_t base[4] = {cb.x, cb.y, cb.z, cb.w};
+            const uint32_t bits[4] = {cm.x & 0xffffu, cm.x >> 16, cm.y & 0xffffu, cm.y >> 16};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if ((bits[r] >> j) & 1u) dA[base[r] + __popc(bits[r] & below)] = acc[r] * s;
+        }
+    }
+}
+
 // DO_CSR / DO_BCSR compile out a part the plan does not have (register
 // footprint of a one-part launch).
 template <class TB, class TG, int VEC, int LPR, int BVEC, int NKR, bool DO_CSR, bool DO_BCSR>
@@ -290,9 +385,14 @@ __global__ __launch_bounds__(256) void k_sddmm(SddArgs a, uint32_t g_bcsr, uint3
     const uint32_t bid = blockIdx.x;
     const int w = wave_id();
     if (bid < g_bcsr) {
-        if constexpr (DO_BCSR)
-            sdd_bcsr_wg<TB, TG, BVEC, NKR>(a, (int64_t)xcd_remap(bid, g_bcsr, remap),
-                                           reinterpret_cast<TG*>(lds_raw));
+        if constexpr (DO_BCSR) {
+            // BVEC 8: the FP16 MFMA form, NKR steps of 32 columns
+            if constexpr (BVEC == 8)
+                sdd_bcsr_wg_h<NKR>(a, (int64_t)xcd_remap(bid, g_bcsr, remap), lds_raw);
+            else
+                sdd_bcsr_wg<TB, TG, BVEC, NKR>(a, (int64_t)xcd_remap(bid, g_bcsr, remap),
+                                               reinterpret_cast<TG*>(lds_raw));
+        }
     } else {
         if constexpr (DO_CSR)
             sdd_csr_wave<TB, TG, VEC, LPR>(a, (int64_t)xcd_remap(bid - g_bcsr, g_csr, remap) * 4 + w);
@@ -322,7 +422,9 @@ int launch_sdd(const SubPlan& X, SddArgs a, hipStream_t s) {
     const uint32_t g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
     const uint32_t g_bcsr = X.rb_bcsr ? pad8(X.rb_bcsr) : 0;
     if (g_csr + g_bcsr == 0) return HSPMM_OK;
-    const size_t lds = g_bcsr ? (size_t)16 * (NKR * 4 * BVEC + 4) * sizeof(TG) : 0;
+    const size_t lds = !g_bcsr ? 0
+                       : BVEC == 8 ? (size_t)16 * (NKR * 32 + 8) * 2 + 4 * sizeof(float)
+                                   : (size_t)16 * (NKR * 4 * BVEC + 4) * sizeof(TG);
     const dim3 grid(g_bcsr + g_csr), block(256);
     const int rm = xcd_remap_mode();
     if (g_bcsr && g_csr && hybrid_launch_mode() == 2) {
@@ -395,6 +497,12 @@ int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC,
                 case HSPMM_F16: {
                     const bool v = n % 4 == 0 && ldb % 4 == 0 && lddc % 4 == 0 && aligned(B, 8) && aligned(dC, 16);
                     if (!v) return launch_sdd<half_t, float, 1, 64, 1, 32>(X, a, s);
+                    // the FP16 MFMA form: n a multiple of 8 up to 256, 16-byte rows of B
+                    if (n % 8 == 0 && n <= 256 && ldb % 8 == 0 && aligned(B, 16)) {
+                        if (n <= 128)
+                            HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<half_t, float, 4, LPR, 8, 4>(X, a, s)));
+                        HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<half_t, float, 4, LPR, 8, 8>(X, a, s)));
+                    }
                     HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<half_t, float, 4, LPR, 4, 8>(X, a, s)));
                 }
                 case HSPMM_BF16: {

@@ -28,6 +28,22 @@ def quantized_dense(B, dtype):
     return torch.as_tensor(B).to(dtype).to(torch.float64).numpy()
 
 
+def fp16_slabs(G, row_blocks):
+    """dC as the FP16 SDDMM reads it: each listed 16-row block scaled by the
+    power of two 2^(e-15) that puts its largest magnitude in [2^14, 2^15),
+    rounded to FP16 (nearest even) and scaled back; other rows unchanged."""
+    out = np.array(G, dtype=np.float64, copy=True)
+    for rb in np.asarray(row_blocks):
+        sl = slice(16 * int(rb), min(16 * int(rb) + 16, out.shape[0]))
+        mx = float(np.max(np.abs(out[sl]))) if out[sl].size else 0.0
+        if mx == 0.0 or not np.isfinite(mx):
+            continue
+        e = np.frexp(mx)[1]
+        s = np.ldexp(1.0, int(e) - 15)
+        out[sl] = (out[sl] / s).astype(np.float16).astype(np.float64) * s
+    return out
+
+
 def effective_vals(a_m, row_ptr, vals, dtype):
     """Values of A as the plan stores them, in FP64: FP64 exact, FP32
     rounded, FP16/BF16 quantised per 16-row block (oracle's quantize_ref)."""

@@ -7,7 +7,7 @@ import torch
 
 import gen
 import oracle
-from tests.gpu_util import SPLITS, TOL, effective_vals, make_plan, quantized_dense, to_dev
+from tests.gpu_util import SPLITS, TOL, effective_vals, fp16_slabs, make_plan, quantized_dense, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -39,13 +39,18 @@ def test_backward_vs_oracle(dtype, split):
     Bq = quantized_dense(B, dtype)
     Gq = G.astype(np.float32).astype(np.float64) if od == torch.float32 else G
     ref_db = oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, Aq, Gq)
-    ref_da = oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, Gq, Bq)
+    # FP16: the BCSR-part's SDDMM multiplies FP16 dC (each 16-row slab
+    # rounded after its power-of-two scale) on FP16 matrix cores
+    Gd = fp16_slabs(Gq, plan.export("bcsr_rb")) if dtype == torch.float16 else Gq
+    ref_da = oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, Gd, Bq)
     tol = 1e-12 if dtype == torch.float64 else 1e-5
     assert oracle.rel_err(dB.double().cpu().numpy(), ref_db) <= tol
     assert oracle.rel_err(dA.double().cpu().numpy(), ref_da) <= tol
     # end-to-end against the unquantised problem
     assert oracle.rel_err(dB.double().cpu().numpy(),
                           oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, G)) <= TOL[dtype]
+    assert oracle.rel_err(dA.double().cpu().numpy(),
+                          oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, G, B)) <= TOL[dtype]
 
 
 @pytest.mark.parametrize("split", SPLITS)
