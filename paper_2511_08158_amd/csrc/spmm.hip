@@ -131,20 +131,22 @@ __device__ void csr_wave(const CsrArgs& a, const DenseArgs& d, int64_t wave) {
                     cc[uu] = __shfl(my_col, (u0 + uu) & (LPR - 1), LPR);
                     vv[uu] = __shfl(my_val, (u0 + uu) & (LPR - 1), LPR);
                 }
+                // branch-free gathers: an absent entry or a lane past n
+                // reads row 0 / column 0 and a select drops the value
+                // (power law FP16 n = 64 forward 451 -> 398 us; FP32
+                // unchanged)
                 TB bv[U][VEC];
+                bool ok[U];
 #pragma unroll
                 for (int uu = 0; uu < U; ++uu) {
-                    if (cc[uu] >= 0 && colok && u0 + uu < cnt) {
-                        load_vec<TB, VEC>(B + (int64_t)cc[uu] * d.ldb + col0, bv[uu]);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < VEC; ++v) bv[uu][v] = TB(0);
-                    }
+                    ok[uu] = cc[uu] >= 0 && colok && u0 + uu < cnt;
+                    load_vec<TB, VEC>(B + (int64_t)(ok[uu] ? cc[uu] : 0) * d.ldb + (colok ? col0 : 0), bv[uu]);
                 }
 #pragma unroll
                 for (int uu = 0; uu < U; ++uu)
 #pragma unroll
-                    for (int v = 0; v < VEC; ++v) acc[v] += vv[uu] * Elem<TB>::to_acc(bv[uu][v]);
+                    for (int v = 0; v < VEC; ++v)
+                        acc[v] += vv[uu] * (ok[uu] ? Elem<TB>::to_acc(bv[uu][v]) : acc_t(0));
             }
         }
         if (act && colok) {
@@ -186,17 +188,17 @@ template <> __device__ inline int out_row<double>(int g, int r) { return g + 4 *
 #define HSPMM_STEP_BATCH 1
 #endif
 constexpr int kStepBatch = HSPMM_STEP_BATCH;
-// gathers a CSR lane group keeps in flight: 4, or 2 for FP16/BF16 lane
-// groups of 8 lanes or fewer.  Measured: power law FP16 n = 64 (8 lanes)
-// forward 602 / 529 / 442 us at 8 / 4 / 2; block stencil FP32 n = 128 (32
-// lanes) CSR-only forward 51.3 / 49.7 / 54.3 us; GCN indifferent; on the
-// FP32 structure sweep 2 instead of 4 loses 6 % at n = 16 (4 lanes, up to
-// 2.4x on a banded matrix with 54 entries per row).
+// gathers a CSR lane group keeps in flight: 4, also for FP16/BF16 lane
+// groups of 8 lanes or fewer (HSPMM_CSR_U_NARROW).  With branch-free
+// gathers, power law FP16 n = 64 (8 lanes) forward 456 / 399 / 370 us at
+// 1 / 2 / 4; with a branch around each gather 2 had been best there.  Block
+// stencil FP32 n = 128 (32 lanes) CSR-only forward 51.3 / 49.7 / 54.3 us
+// at 8 / 4 / 2.
 #ifndef HSPMM_CSR_U
 #define HSPMM_CSR_U 4
 #endif
 #ifndef HSPMM_CSR_U_NARROW
-#define HSPMM_CSR_U_NARROW 2
+#define HSPMM_CSR_U_NARROW 4
 #endif
 #ifndef HSPMM_F32_CSR_VEC8
 #define HSPMM_F32_CSR_VEC8 0
@@ -636,7 +638,7 @@ constexpr int bcsr_waves_per_simd() {
     // (VGPR + AGPR count from the compiler's resource usage report); FP16 /
     // BF16 with 4 column groups is held one wave lower, where the fused
     // kernel fits without spilling
-    if (sizeof(TV) == 2) return VEC == 1 ? (WAVE ? 7 : 8) : (BV == 8 ? (WAVE ? 3 : 4) : (WAVE ? 4 : 5));
+    if (sizeof(TV) == 2) return VEC == 1 ? 7 : (BV == 8 ? (WAVE ? 3 : 4) : (WAVE ? 4 : 5));
     if (sizeof(TV) == 8) return VEC == 1 ? 4 : (BNL >= 2 ? 4 : (WAVE ? 8 : 7));
     return VEC == 1 ? (WAVE ? 7 : 6) : (BNL >= 2 ? (WAVE ? 5 : 4) : 8);
 }
