@@ -126,17 +126,31 @@ __device__ void sdd_csr_wave(const SddArgs& a, int64_t wave) {
                     }
                 }
             } else {
-                for (int64_t c0 = col0; c0 < a.n; c0 += (int64_t)LPR * VEC) {
+                // several panels of LPR * VEC columns: every lane takes the
+                // same number of panels (the shuffles need every lane of the
+                // group active), a lane past n reads column 0 and its
+                // products are dropped
+                for (int64_t cb = 0; cb < a.n; cb += (int64_t)LPR * VEC) {
+                    const int64_t c0 = cb + col0;
+                    const bool cok = c0 < a.n;
                     TG gv[VEC];
-                    load_as<TG, VEC>(dC + (int64_t)row * a.lddc + c0, gv);
+                    load_as<TG, VEC>(dC + (int64_t)row * a.lddc + (cok ? c0 : 0), gv);
 #pragma unroll
-                    for (int uu = 0; uu < U; ++uu) {
-                        const int c = __shfl(my_col, (u0 + uu) & (LPR - 1), LPR);
-                        if (c >= 0 && u0 + uu < cnt) {
-                            TG bv[VEC];
-                            load_as<TB, VEC>(B + (int64_t)c * a.ldb + c0, bv);
+                    for (int ub = 0; ub < U; ub += UB) {
+                        TG bv[UB][VEC];
+                        bool ok[UB];
 #pragma unroll
-                            for (int v = 0; v < VEC; ++v) part[uu] += gv[v] * bv[v];
+                        for (int k = 0; k < UB; ++k) {
+                            const int c = __shfl(my_col, (u0 + ub + k) & (LPR - 1), LPR);
+                            ok[k] = c >= 0 && u0 + ub + k < cnt && cok;
+                            load_as<TB, VEC>(B + (int64_t)(ok[k] ? c : 0) * a.ldb + (cok ? c0 : 0), bv[k]);
+                        }
+#pragma unroll
+                        for (int k = 0; k < UB; ++k) {
+                            TG dot = TG(0);
+#pragma unroll
+                            for (int v = 0; v < VEC; ++v) dot += gv[v] * bv[k][v];
+                            part[ub + k] += ok[k] ? dot : TG(0);
                         }
                     }
                 }

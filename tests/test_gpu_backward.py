@@ -53,6 +53,34 @@ def test_backward_vs_oracle(dtype, split):
                           oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, G, B)) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16, torch.bfloat16])
+@pytest.mark.parametrize("n", [5, 40, 200, 300])
+@pytest.mark.parametrize("split", ["bcsr", "csr"])
+def test_sddmm_forms_by_width(dtype, n, split):
+    """Every form of the SDDMM against the oracle on the inputs as the
+    kernels read them: one column per lane (n = 5), the dC slab held in LDS
+    (n = 40), FP16's matrix-core form up to n = 256, dC read from global
+    memory per step (n = 200 and 300 for the FP32-MFMA forms) and CSR lane
+    groups that loop over several column panels (n = 300)."""
+    print(f"sddmm forms dtype={dtype} n={n} split={split}", flush=True)
+    a = gen.random_csr(31, 150, 170, 0.09)
+    g = np.random.default_rng(8)
+    B = g.standard_normal((a.k, n))
+    G = g.standard_normal((a.m, n))
+    plan = make_plan(hs, a, dtype, split, backward=True)
+    od = torch.float64 if dtype == torch.float64 else torch.float32
+    dB, dA = plan.backward(to_dev(B, dtype), to_dev(G, od))
+    torch.cuda.synchronize()
+    Bq = quantized_dense(B, dtype)
+    Gq = G.astype(np.float32).astype(np.float64) if od == torch.float32 else G
+    if dtype == torch.float16 and split == "bcsr" and n % 8 == 0 and n <= 256:
+        Gq = fp16_slabs(Gq, plan.export("bcsr_rb"))
+    ref = oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, Gq, Bq)
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    assert oracle.rel_err(dA.double().cpu().numpy(), ref) <= tol
+    assert oracle.rel_err(dA.double().cpu().numpy(), oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, G, B)) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("split", SPLITS)
 def test_backward_integer_bitwise(split):
     a = gen.random_csr(3, 190, 170, 0.07, dist="int")
