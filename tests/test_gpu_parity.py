@@ -93,6 +93,40 @@ def test_ragged_all_splits(dtype, n):
         assert oracle.rel_err(C, ref_k) <= kt, split
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16])
+def test_split_launch_equals_fused(dtype, monkeypatch):
+    """HSPMM_HYBRID_LAUNCH=2 launches the two parts as two kernels instead of
+    one fused launch: the same per-row work, so C, dB and dA are bitwise
+    equal to the fused launch's."""
+    a = gen.random_csr(9, 420, 390, 0.04)
+    g = np.random.default_rng(6)
+    rows = np.repeat(np.arange(a.m), np.diff(a.row_ptr))
+    keep = (rows < 200) | (rows >= 260)
+    # rows 200..259 hold a dense 60 x 40 block: BCSR row blocks; the rest CSR
+    extra_r = np.repeat(np.arange(200, 260), 40)
+    extra_c = np.tile(np.arange(100, 140), 60)
+    a = gen.csr_from_coo(a.m, a.k, np.concatenate([rows[keep], extra_r]),
+                         np.concatenate([a.col_idx[keep], extra_c]),
+                         np.concatenate([a.vals[keep], g.standard_normal(extra_r.size)]))
+    plan = make_plan(hs, a, dtype, "boundary", backward=True, r_boundary=208)
+    info = plan.info()
+    assert info["rows_csr"] == 208 and info["rb_bcsr"] == (a.m - 208 + 15) // 16
+    B = g.standard_normal((a.k, 48))
+    G = g.standard_normal((a.m, 48))
+    od = torch.float64 if dtype == torch.float64 else torch.float32
+    out = {}
+    for mode in ("1", "2"):
+        monkeypatch.setenv("HSPMM_HYBRID_LAUNCH", mode)
+        C = plan.run(to_dev(B, dtype))
+        dB, dA = plan.backward(to_dev(B, dtype), to_dev(G, od))
+        torch.cuda.synchronize()
+        out[mode] = [t.double().cpu().numpy() for t in (C, dB, dA)]
+    monkeypatch.delenv("HSPMM_HYBRID_LAUNCH", raising=False)
+    for x, y in zip(out["1"], out["2"]):
+        assert np.array_equal(x, y)
+    assert oracle.rel_err(out["1"][0], oracle_forward(a, B)) <= TOL[dtype]
+
+
 def test_empty_and_degenerate():
     # empty rows, an empty matrix, nnz = 0, a single column
     a = gen.csr_from_coo(40, 30, np.array([3, 3, 17]), np.array([0, 29, 5]), np.array([1.0, 2.0, 3.0]))
