@@ -564,18 +564,24 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
     int64_t window = HSPMM_SORT_WINDOW;
     while (window > 64 && window * 32 > (int64_t)vs.size()) window >>= 1;
     if (window > 1) {
-        auto len_class = [&](int32_t x) -> int32_t {
-            const int32_t len = ve[x] - vs[x];
-            int32_t c = 0;
-            while ((len >> c) > 1) ++c;
-            return c;
-        };
-        std::vector<int32_t> idx(vs.size());
-        for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int32_t)i;
-        for (size_t w0 = 0; w0 < idx.size(); w0 += (size_t)window) {
-            const size_t w1 = std::min(idx.size(), w0 + (size_t)window);
-            std::stable_sort(idx.begin() + w0, idx.begin() + w1,
-                             [&](int32_t x, int32_t y) { return len_class(x) > len_class(y); });
+        // a stable counting sort per window on the class, longest first
+        const size_t nv = vs.size();
+        std::vector<uint8_t> cls(nv);
+        for (size_t i = 0; i < nv; ++i) {
+            const uint32_t len = (uint32_t)(ve[i] - vs[i]);
+            cls[i] = len > 1 ? (uint8_t)(31 - __builtin_clz(len)) : 0;
+        }
+        std::vector<int32_t> idx(nv);
+        for (size_t w0 = 0; w0 < nv; w0 += (size_t)window) {
+            const size_t w1 = std::min(nv, w0 + (size_t)window);
+            size_t cnt[32] = {0}, off[32];
+            for (size_t i = w0; i < w1; ++i) ++cnt[cls[i]];
+            size_t at = w0;
+            for (int c = 31; c >= 0; --c) {
+                off[c] = at;
+                at += cnt[c];
+            }
+            for (size_t i = w0; i < w1; ++i) idx[off[cls[i]]++] = (int32_t)i;
         }
         auto apply = [&](std::vector<int32_t>& v) {
             std::vector<int32_t> t(v.size());
