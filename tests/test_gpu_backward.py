@@ -54,14 +54,14 @@ def test_backward_vs_oracle(dtype, split):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16, torch.bfloat16])
-@pytest.mark.parametrize("n", [5, 40, 200, 300])
+@pytest.mark.parametrize("n", [5, 40, 200, 300, 1024])
 @pytest.mark.parametrize("split", ["bcsr", "csr"])
 def test_sddmm_forms_by_width(dtype, n, split):
     """Every form of the SDDMM against the oracle on the inputs as the
     kernels read them: one column per lane (n = 5), the dC slab held in LDS
     (n = 40), FP16's matrix-core form up to n = 256, dC read from global
-    memory per step (n = 200 and 300 for the FP32-MFMA forms) and CSR lane
-    groups that loop over several column panels (n = 300)."""
+    memory per step (n = 200, 300 and 1024 for the FP32-MFMA forms) and CSR
+    lane groups that loop over several column panels (n = 300, 1024)."""
     print(f"sddmm forms dtype={dtype} n={n} split={split}", flush=True)
     a = gen.random_csr(31, 150, 170, 0.09)
     g = np.random.default_rng(8)

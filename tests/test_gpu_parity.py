@@ -75,7 +75,7 @@ def test_identity_and_permutation_bitwise():
 # ragged shapes, several tiles, every dtype and split
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16, torch.bfloat16])
-@pytest.mark.parametrize("n", [1, 3, 16, 36, 64, 130, 256])
+@pytest.mark.parametrize("n", [1, 3, 16, 36, 64, 130, 256, 520])
 def test_ragged_all_splits(dtype, n):
     print(f"ragged dtype={dtype} n={n}", flush=True)
     a = gen.random_csr(5, 357, 291, 0.05)
