@@ -135,10 +135,10 @@ int hybrid_spmm_run(hspmm_plan_t p, int64_t n, const void* B, int64_t ldb,
  *   B: as in hybrid_spmm_run (dtype = compute); dC: m x n, FP64 for F64
  *      plans, FP32 otherwise.
  * F16/BF16 plans compute dB in FP32 from the stored (quantised) values.
- * dA accumulates in FP32; for F16 plans the BCSR-part's rows (n a multiple
- * of 8, at most 256) first round each 16-row slab of dC to FP16 after an
- * exact power-of-two scale (largest magnitude in [2^14, 2^15)), one FP16
- * rounding per dC element.  Errors: ARG, NO_BACKWARD (dB requested without
+ * dA accumulates in FP32; for F16/BF16 plans the BCSR-part's rows (n a
+ * multiple of 8, at most 256) first round each 16-row slab of dC to the
+ * compute type after an exact power-of-two scale (largest magnitude in
+ * [2^14, 2^15)), one rounding per dC element.  Errors: ARG, NO_BACKWARD (dB requested without
  * want_backward), HIP, OOM. */
 int hybrid_spmm_backward(hspmm_plan_t p, int64_t n, const void* B, int64_t ldb,
                          const void* dC, int64_t lddc, void* dB, int64_t lddb,

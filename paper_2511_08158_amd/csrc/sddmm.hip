@@ -318,28 +318,41 @@ __device__ void sdd_bcsr_wg(const SddArgs& a, int64_t slot, TG* lds) {
     }
 }
 
-// FP16 row blocks on 16x16x32 MFMAs (K = 32 columns of n per step).  The
-// 16 x n slab of dC is staged in LDS as FP16 after an exact power-of-two
-// scale s that puts its largest magnitude in [2^14, 2^15) (no overflow, and
-// the FP16 normal range below it is kept), so the only change to dC is one
-// FP16 rounding per element, as for B; products accumulate in FP32 and the
-// results are multiplied back by s.  Lane (i, q) supplies dC row i and B
-// row j of the step's columns 8q .. 8q + 7: one 16-byte LDS read and one
-// 16-byte gather per step.  The launcher guarantees n <= 32 NKH, n a
-// multiple of 8, 16-byte aligned rows of B and dC.
-template <int NKH>
+// FP16 / BF16 row blocks on 16x16x32 MFMAs (K = 32 columns of n per step).
+// The 16 x n slab of dC is staged in LDS in the compute type after an exact
+// power-of-two scale s that puts its largest magnitude in [2^14, 2^15) (no
+// FP16 overflow, and the FP16 normal range below it is kept), so the only
+// change to dC is one rounding per element, as for B; products accumulate
+// in FP32 and the results are multiplied back by s.  Lane (i, q) supplies
+// dC row i and B row j of the step's columns 8q .. 8q + 7: one 16-byte LDS
+// read and one 16-byte gather per step.  The launcher guarantees
+// n <= 32 NKH, n a multiple of 8, 16-byte aligned rows of B and dC.
+template <class T> struct Mfma32;
+template <> struct Mfma32<half_t> {
+    typedef h8_t v8;
+    typedef _Float16 v4 __attribute__((ext_vector_type(4)));
+    static __device__ f4_t run(v8 a, v8 b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+template <> struct Mfma32<bf16_t> {
+    typedef b8_t v8;
+    typedef __bf16 v4 __attribute__((ext_vector_type(4)));
+    static __device__ f4_t run(v8 a, v8 b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+template <class TB, int NKH>
 __device__ void sdd_bcsr_wg_h(const SddArgs& a, int64_t slot, unsigned char* smem) {
+    typedef typename Mfma32<TB>::v8 v8;
+    typedef typename Mfma32<TB>::v4 v4;
     if (slot >= a.n_rb) return;  // uniform over the workgroup
     constexpr int NMAX = 32 * NKH;
     constexpr int LDR = NMAX + 8;  // halfs per LDS row: rows stay 16-byte aligned
     constexpr int NV = NMAX / 64;  // float4 of the slab per thread
-    half_t* lds = reinterpret_cast<half_t*>(smem);
-    float* red = reinterpret_cast<float*>(smem + 16 * LDR * sizeof(half_t));
+    TB* lds = reinterpret_cast<TB*>(smem);
+    float* red = reinterpret_cast<float*>(smem + 16 * LDR * sizeof(TB));
     const int lane = threadIdx.x & 63, w = wave_id(), j = lane & 15, q = lane >> 4;
     const int rb = a.rb[slot];
     const int b0 = a.blk_ptr[slot];
     const int cnt = a.blk_cnt[slot];
-    const half_t* __restrict__ B = static_cast<const half_t*>(a.B);
+    const TB* __restrict__ B = static_cast<const TB*>(a.B);
     const float* __restrict__ dC = static_cast<const float*>(a.dC);
     float* __restrict__ dA = static_cast<float*>(a.dA);
     f4_t x[NV];
@@ -367,14 +380,13 @@ __device__ void sdd_bcsr_wg_h(const SddArgs& a, int64_t slot, unsigned char* sme
     for (int v = 0; v < NV; ++v) {
         const int idx = (threadIdx.x + 256 * v) * 4;
         const int i = idx / NMAX, c = idx - i * NMAX;
-        typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
-        h4_t hv;
+        v4 hv;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) hv[t] = (half_t)(x[v][t] * inv);
-        *reinterpret_cast<h4_t*>(lds + i * LDR + c) = hv;
+        for (int t = 0; t < 4; ++t) hv[t] = (TB)(x[v][t] * inv);
+        *reinterpret_cast<v4*>(lds + i * LDR + c) = hv;
     }
     __syncthreads();
-    const half_t* __restrict__ arow = lds + j * LDR + q * 8;
+    const TB* __restrict__ arow = lds + j * LDR + q * 8;
     const int64_t chunk0 = a.chunk_ptr[slot];
     const uint32_t below = (1u << j) - 1u;
     for (int it0 = 0; 16 * w + 64 * it0 < cnt; it0 += 4) {
@@ -391,17 +403,17 @@ __device__ void sdd_bcsr_wg_h(const SddArgs& a, int64_t slot, unsigned char* sme
             const uint2 cm = *reinterpret_cast<const uint2*>(a.chunk_mask + ci * 16 + 4 * q);
             // unconditional gathers: a tile past the row block's end reads
             // row 0 of B, a step past n reads column 0 against zeros in LDS
-            h8_t bv[NKH];
+            v8 bv[NKH];
 #pragma unroll
             for (int t = 0; t < NKH; ++t) {
                 const int64_t c = (int64_t)t * 32 + q * 8;
-                bv[t] = *reinterpret_cast<const h8_t*>(B + (int64_t)bc * a.ldb + (c < a.n ? c : 0));
+                bv[t] = *reinterpret_cast<const v8*>(B + (int64_t)bc * a.ldb + (c < a.n ? c : 0));
             }
             f4_t acc = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int t = 0; t < NKH; ++t) {
-                const h8_t av = *reinterpret_cast<const h8_t*>(arow + t * 32);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv[t], acc, 0, 0, 0);
+                const v8 av = *reinterpret_cast<const v8*>(arow + t * 32);
+                acc = Mfma32<TB>::run(av, bv[t], acc);
             }
             const int32_t base[4] = {cb.x, cb.y, cb.z, cb.w};
             const uint32_t bits[4] = {cm.x & 0xffffu, cm.x >> 16, cm.y & 0xffffu, cm.y >> 16};
@@ -421,9 +433,9 @@ __global__ __launch_bounds__(256) void k_sddmm(SddArgs a, uint32_t g_bcsr, uint3
     const int w = wave_id();
     if (bid < g_bcsr) {
         if constexpr (DO_BCSR) {
-            // BVEC 8: the FP16 MFMA form, NKR steps of 32 columns
+            // BVEC 8: the FP16 / BF16 MFMA form, NKR steps of 32 columns
             if constexpr (BVEC == 8)
-                sdd_bcsr_wg_h<NKR>(a, (int64_t)xcd_remap(bid, g_bcsr, remap), lds_raw);
+                sdd_bcsr_wg_h<TB, NKR>(a, (int64_t)xcd_remap(bid, g_bcsr, remap), lds_raw);
             else
                 sdd_bcsr_wg<TB, TG, BVEC, NKR>(a, (int64_t)xcd_remap(bid, g_bcsr, remap),
                                                reinterpret_cast<TG*>(lds_raw));
@@ -552,6 +564,14 @@ int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC,
                 case HSPMM_BF16: {
                     const bool v = n % 4 == 0 && ldb % 4 == 0 && lddc % 4 == 0 && aligned(B, 8) && aligned(dC, 16);
                     if (!v) return launch_sdd<bf16_t, float, 1, 64, 1, 32>(X, a, s);
+                    // the BF16 MFMA form: n a multiple of 8 up to 256, 16-byte rows of B
+                    if (n % 8 == 0 && n <= 256 && ldb % 8 == 0 && aligned(B, 16)) {
+                        if (n <= 128)
+                            HSPMM_LPR_SWITCH(lpr_for(n, HSPMM_SDD_H_VEC),
+                                             return (launch_sdd<bf16_t, float, HSPMM_SDD_H_VEC, LPR, 8, 4>(X, a, s)));
+                        HSPMM_LPR_SWITCH(lpr_for(n, HSPMM_SDD_H_VEC),
+                                         return (launch_sdd<bf16_t, float, HSPMM_SDD_H_VEC, LPR, 8, 8>(X, a, s)));
+                    }
                     if (n % 8 == 0 && ldb % 8 == 0 && aligned(B, 16))
                         HSPMM_LPR_SWITCH(lpr_for(n, HSPMM_SDD_H_VEC),
                                          return (launch_sdd<bf16_t, float, HSPMM_SDD_H_VEC, LPR, 4, 8>(X, a, s)));

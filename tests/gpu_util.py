@@ -28,10 +28,11 @@ def quantized_dense(B, dtype):
     return torch.as_tensor(B).to(dtype).to(torch.float64).numpy()
 
 
-def fp16_slabs(G, row_blocks):
-    """dC as the FP16 SDDMM reads it: each listed 16-row block scaled by the
-    power of two 2^(e-15) that puts its largest magnitude in [2^14, 2^15),
-    rounded to FP16 (nearest even) and scaled back; other rows unchanged."""
+def rounded_slabs(G, row_blocks, dtype=torch.float16):
+    """dC as the FP16/BF16 SDDMM's matrix-core form reads it: each listed
+    16-row block scaled by the power of two 2^(e-15) that puts its largest
+    magnitude in [2^14, 2^15), rounded to `dtype` (nearest even) and scaled
+    back; other rows unchanged."""
     out = np.array(G, dtype=np.float64, copy=True)
     for rb in np.asarray(row_blocks):
         sl = slice(16 * int(rb), min(16 * int(rb) + 16, out.shape[0]))
@@ -40,7 +41,8 @@ def fp16_slabs(G, row_blocks):
             continue
         e = np.frexp(mx)[1]
         s = np.ldexp(1.0, int(e) - 15)
-        out[sl] = (out[sl] / s).astype(np.float16).astype(np.float64) * s
+        q = torch.as_tensor(out[sl] / s).to(torch.float32).to(dtype).to(torch.float64).numpy()
+        out[sl] = q * s
     return out
 
 

@@ -7,7 +7,7 @@ import torch
 
 import gen
 import oracle
-from tests.gpu_util import SPLITS, TOL, effective_vals, fp16_slabs, make_plan, quantized_dense, to_dev
+from tests.gpu_util import SPLITS, TOL, effective_vals, make_plan, quantized_dense, rounded_slabs, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -39,9 +39,10 @@ def test_backward_vs_oracle(dtype, split):
     Bq = quantized_dense(B, dtype)
     Gq = G.astype(np.float32).astype(np.float64) if od == torch.float32 else G
     ref_db = oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, Aq, Gq)
-    # FP16: the BCSR-part's SDDMM multiplies FP16 dC (each 16-row slab
-    # rounded after its power-of-two scale) on FP16 matrix cores
-    Gd = fp16_slabs(Gq, plan.export("bcsr_rb")) if dtype == torch.float16 else Gq
+    # FP16/BF16: the BCSR-part's SDDMM multiplies dC rounded to the compute
+    # type (each 16-row slab after its power-of-two scale) on matrix cores
+    half = dtype in (torch.float16, torch.bfloat16)
+    Gd = rounded_slabs(Gq, plan.export("bcsr_rb"), dtype) if half else Gq
     ref_da = oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, Gd, Bq)
     tol = 1e-12 if dtype == torch.float64 else 1e-5
     assert oracle.rel_err(dB.double().cpu().numpy(), ref_db) <= tol
@@ -59,7 +60,7 @@ def test_backward_vs_oracle(dtype, split):
 def test_sddmm_forms_by_width(dtype, n, split):
     """Every form of the SDDMM against the oracle on the inputs as the
     kernels read them: one column per lane (n = 5), the dC slab held in LDS
-    (n = 40), FP16's matrix-core form up to n = 256, dC read from global
+    (n = 40), the FP16/BF16 matrix-core form up to n = 256, dC read from global
     memory per step (n = 200, 300 and 1024 for the FP32-MFMA forms) and CSR
     lane groups that loop over several column panels (n = 300, 1024)."""
     print(f"sddmm forms dtype={dtype} n={n} split={split}", flush=True)
@@ -73,8 +74,8 @@ def test_sddmm_forms_by_width(dtype, n, split):
     torch.cuda.synchronize()
     Bq = quantized_dense(B, dtype)
     Gq = G.astype(np.float32).astype(np.float64) if od == torch.float32 else G
-    if dtype == torch.float16 and split == "bcsr" and n % 8 == 0 and n <= 256:
-        Gq = fp16_slabs(Gq, plan.export("bcsr_rb"))
+    if dtype in (torch.float16, torch.bfloat16) and split == "bcsr" and n % 8 == 0 and n <= 256:
+        Gq = rounded_slabs(Gq, plan.export("bcsr_rb"), dtype)
     ref = oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, Gq, Bq)
     tol = 1e-12 if dtype == torch.float64 else 1e-5
     assert oracle.rel_err(dA.double().cpu().numpy(), ref) <= tol
@@ -115,7 +116,7 @@ def test_concurrent_backward_equals_sequential(split, monkeypatch):
                                                G.double().cpu().numpy(), B.double().cpu().numpy())) <= 1e-5
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16, torch.bfloat16])
 def test_sddmm_wide_row_blocks(dtype):
     """Row blocks with thousands of tiles (many rounds of 64 tiles per wave),
     a ragged last row block, empty rows and unsorted duplicated input: the
