@@ -127,6 +127,40 @@ def test_split_launch_equals_fused(dtype, monkeypatch):
     assert oracle.rel_err(out["1"][0], oracle_forward(a, B)) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16, torch.bfloat16])
+@pytest.mark.parametrize("pad", [3, 8])
+def test_leading_dimensions(dtype, pad):
+    """B and C as column slices of wider matrices (ld = n + pad): pad 8
+    keeps 16-byte rows (the vector kernels, bitwise equal to contiguous
+    operands), pad 3 breaks them (the one-column-per-lane kernels, checked
+    against the oracle); the backward reads B with the same leading
+    dimension."""
+    a = gen.random_csr(23, 300, 260, 0.05)
+    n = 40
+    g = np.random.default_rng(pad)
+    B = g.standard_normal((a.k, n))
+    G = g.standard_normal((a.m, n))
+    od = torch.float64 if dtype == torch.float64 else torch.float32
+    for split in ("auto", "csr", "bcsr"):
+        plan = make_plan(hs, a, dtype, split, backward=True)
+        Bc = to_dev(B, dtype)
+        Bw = torch.zeros((a.k, n + pad), dtype=dtype, device=Bc.device)
+        Bw[:, :n] = Bc
+        Cw = torch.full((a.m, n + pad), 7.0, dtype=od, device=Bc.device)
+        C1 = plan.run(Bc)
+        C2 = plan.run(Bw[:, :n], out=Cw[:, :n])
+        dB1, dA1 = plan.backward(Bc, to_dev(G, od))
+        dB2, dA2 = plan.backward(Bw[:, :n], to_dev(G, od))
+        torch.cuda.synchronize()
+        assert torch.all(Cw[:, n:] == 7.0), split          # nothing written past n
+        c1, c2 = C1.double().cpu().numpy(), C2.double().cpu().numpy()
+        if pad == 8:
+            assert np.array_equal(c1, c2), split
+            assert torch.equal(dB1, dB2) and torch.equal(dA1, dA2), split
+        assert oracle.rel_err(c2, oracle_forward(a, B)) <= TOL[dtype], split
+        assert oracle.rel_err(dA2.double().cpu().numpy(), oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, G, B)) <= TOL[dtype], split
+
+
 def test_empty_and_degenerate():
     # empty rows, an empty matrix, nnz = 0, a single column
     a = gen.csr_from_coo(40, 30, np.array([3, 3, 17]), np.array([0, 29, 5]), np.array([1.0, 2.0, 3.0]))
