@@ -759,7 +759,10 @@ __global__ __launch_bounds__(BT) void k_long_reduce(const int32_t* __restrict__ 
 }
 
 // Launch of the reduction above: V columns per lane when the partial rows
-// allow 16-byte loads, and 1024 threads when some row has many partials.
+// allow 16-byte loads, and 1024 threads when, at 256, the longest row would
+// leave more than 8 partials to each lane group (256 / L groups): a row of
+// 490 partials at n = 256 needs the extra groups, while rows of at most 79
+// at n = 64 FP16 keep 256 (power law forward's reduction 38 -> 9 us).
 template <class TC, class Acc>
 void launch_long_reduce(const SubPlan& X, const DenseArgs& d, hipStream_t s) {
     constexpr int VW = 16 / (int)sizeof(Acc);
@@ -768,7 +771,7 @@ void launch_long_reduce(const SubPlan& X, const DenseArgs& d, hipStream_t s) {
     int L = 1;
     while (L < 64 && (int64_t)L * V < d.n) L <<= 1;
     const dim3 grid((unsigned)X.n_long, (unsigned)ceil_div(d.n, (int64_t)64 * V));
-    const bool big = X.max_long_cnt >= 64;
+    const bool big = (int64_t)X.max_long_cnt * L > 8 * 256;
     const Acc* ws = static_cast<const Acc*>(d.ws);
     TC* C = static_cast<TC*>(d.C);
 #define HSPMM_LR(VV, BB)                                                                                     \
