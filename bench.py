@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--gcn-train", action="store_true",
                     help="time a two-layer graph-convolution training loop on the 232,965-node graph")
     ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--no-vendor", action="store_true", help="skip the vendor CSR product timed for context")
     ap.add_argument("--no-other-dtypes", action="store_true",
                     help="skip the same step in the other compute precisions (stencil only)")
     return ap.parse_args()
@@ -481,6 +482,35 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": per_launch[dom]},
     }
+
+    if not args.no_vendor:
+        # context only: the vendor CSR product (torch.sparse over hipSPARSE)
+        # on the same matrix and B, forward only, HIP events on the stream
+        try:
+            crow = torch.tensor(a.row_ptr, dtype=torch.int64, device=dev)
+            coli = torch.tensor(a.col_idx, dtype=torch.int64, device=dev)
+            Av = torch.sparse_csr_tensor(crow, coli, vals.to(tdtype), size=(a.m, a.k))
+            Cv = Av @ B
+            for _ in range(3):
+                Cv = Av @ B
+            reps_v = 20
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps_v):
+                Cv = Av @ B
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tv = e0.elapsed_time(e1) / reps_v * 1e3
+            Ch = hyb.run(B)
+            torch.cuda.synchronize()
+            line["vendor_csr_forward"] = {
+                "library": "torch.sparse CSR @ dense (hipSPARSE)", "us": round(tv, 2),
+                "gflops": round(2.0 * a.nnz * n / (tv * 1e-6) / 1e9, 1),
+                "hybrid_forward_speedup": round(tv / kt["forward"], 3),
+                "agreement_rel_err": float(f"{rel_err(Cv.double().cpu().numpy(), Ch.double().cpu().numpy()):.2e}")}
+            del Av, Cv
+        except Exception as ex:  # the vendor path is optional context
+            line["vendor_csr_forward"] = {"error": str(ex)[:200]}
 
     if args.workload == "stencil" and not args.no_other_dtypes:
         # the same step in the other precisions of the method: GFLOP/s of the
