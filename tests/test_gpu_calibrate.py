@@ -82,3 +82,24 @@ def test_calibrate_one_part(split):
         assert cal["x_max"] == 0 and all(v == 0 for v in cal["cand_x"]) and cal["best"][0] == 0
     _check_fit(cal)
     assert np.array_equal(plan.run(B).cpu().numpy(), C0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float16, torch.bfloat16])
+def test_calibrate_mixed_plan_other_dtypes(dtype):
+    """The calibrated partition caps each part's workgroups, so the BCSR
+    forms of every precision walk several units per workgroup: C stays
+    bitwise the same, and the backward after calibration is unchanged."""
+    print(f"calibration dtype={dtype}", flush=True)
+    a, b = gen.config2(grid=48)
+    plan = make_plan(hs, a, dtype, "boundary", backward=True, r_boundary=a.m // 2)
+    B = to_dev(b, dtype)
+    od = torch.float64 if dtype == torch.float64 else torch.float32
+    G = to_dev(gen.dense(0, gen.GRAD, a.m, b.shape[1]), od)
+    C0 = plan.run(B).cpu().numpy()
+    dB0, dA0 = plan.backward(B, G)
+    cal = plan.calibrate(B, reps=2)
+    _check_fit(cal)
+    assert np.array_equal(plan.run(B).cpu().numpy(), C0)
+    dB1, dA1 = plan.backward(B, G)
+    torch.cuda.synchronize()
+    assert torch.equal(dB0, dB1) and torch.equal(dA0, dA1)
