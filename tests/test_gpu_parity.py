@@ -358,6 +358,33 @@ def test_rerun_bitwise_identical_and_update_values():
     assert oracle.rel_err(_run(plan, b, torch.float32), oracle_forward(a2, b)) <= 1e-5
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float16, torch.bfloat16])
+@pytest.mark.parametrize("split", ["auto", "csr", "bcsr"])
+def test_update_values_rescales(dtype, split):
+    """New values of another magnitude through update_values: the per-row-
+    block scales of FP16/BF16 are recomputed (values 1e4 times larger would
+    overflow FP16 under the old scales) and C, dB and dA follow the new
+    values."""
+    a = gen.random_csr(14, 200, 180, 0.08)
+    g = np.random.default_rng(12)
+    B = g.standard_normal((a.k, 32))
+    G = g.standard_normal((a.m, 32))
+    plan = make_plan(hs, a, dtype, split, backward=True)
+    v2 = g.standard_normal(a.nnz) * 1e4
+    plan.update_values(to_dev(v2))
+    a2 = gen.Csr(a.m, a.k, a.row_ptr, a.col_idx, v2)
+    od = torch.float64 if dtype == torch.float64 else torch.float32
+    C = _run(plan, B, dtype)
+    dB, dA = plan.backward(to_dev(B, dtype), to_dev(G, od))
+    torch.cuda.synchronize()
+    assert np.isfinite(C).all()
+    assert oracle.rel_err(C, oracle_forward(a2, B)) <= TOL[dtype]
+    assert oracle.rel_err(dB.double().cpu().numpy(),
+                          oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, v2, G)) <= TOL[dtype]
+    # dA does not depend on the values
+    assert oracle.rel_err(dA.double().cpu().numpy(), oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, G, B)) <= TOL[dtype]
+
+
 # ---------------------------------------------------------------------------
 # config 2 (block stencil, FP32, N = 128) at full size
 # ---------------------------------------------------------------------------
