@@ -190,6 +190,39 @@ def test_gradcheck_tiny_fp64():
         assert torch.autograd.gradcheck(lambda v, b: hs.spmm(plan, v, b), (vals, B), eps=1e-6, atol=1e-9)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16, torch.bfloat16])
+def test_autograd_low_precision(dtype):
+    """spmm's autograd function in FP32/FP16/BF16 with learnable values:
+    every forward re-packs the values (quantised per row block for
+    FP16/BF16); the gradients of vals and B match the products the library
+    computes directly, and both match the oracle within the precision's
+    tolerance."""
+    a = gen.random_csr(8, 150, 140, 0.07)
+    dev = torch.device("cuda:0")
+    g = np.random.default_rng(9)
+    vals = torch.tensor(a.vals, device=dev, dtype=torch.float32, requires_grad=True)
+    Bn = g.standard_normal((a.k, 24))
+    Gn = g.standard_normal((a.m, 24))
+    B = to_dev(Bn, dtype).requires_grad_(True)
+    plan = hs.Plan(a.row_ptr, a.col_idx, vals.detach(), (a.m, a.k), compute=dtype, split="auto", backward=True)
+    for step in range(2):
+        C = hs.spmm(plan, vals, B)
+        C.backward(to_dev(Gn, torch.float32))
+        torch.cuda.synchronize()
+        dB_ref, dA_ref = plan.backward(B.detach(), to_dev(Gn, torch.float32))
+        torch.cuda.synchronize()
+        assert torch.equal(B.grad.float(), dB_ref.to(B.dtype).float())
+        assert torch.equal(vals.grad, dA_ref.to(vals.dtype))
+        assert oracle.rel_err(vals.grad.double().cpu().numpy(),
+                              oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, Gn, Bn)) <= TOL[dtype]
+        with torch.no_grad():
+            vals.mul_(2.0)   # a new version of the values: the next forward re-packs them
+        vals.grad = None
+        B.grad = None
+    assert oracle.rel_err(C.detach().double().cpu().numpy(),
+                          oracle.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals * 2.0, Bn)) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("split", SPLITS)
 @pytest.mark.parametrize("n", [64, 128])
