@@ -433,6 +433,13 @@ def main():
         cpu_line = {"value": round(6.0 * a.nnz * n / tc / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
                     "kind": "oracle",
                     "sample": f"{reps} full fwd+bwd passes of the FP64 oracle on the same workload"}
+        # one single-threaded pass beside it (the oracle sums each row in
+        # order whatever the thread count, so the outputs are the same)
+        t1 = time.perf_counter()
+        orc.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, b_used, nthreads=1)
+        orc.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, g, nthreads=1)
+        orc.sddmm(a.m, a.k, a.row_ptr, a.col_idx, g, b_used, nthreads=1)
+        cpu_line["single_thread_value"] = round(6.0 * a.nnz * n / (time.perf_counter() - t1) / 1e9, 3)
         refs = {"C": r_c, "dB": r_db, "dA": r_da}
         # the unquantised problem: end-to-end reference of the other precisions
         if dt == "f32" and np.array_equal(b_used, b):
