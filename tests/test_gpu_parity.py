@@ -405,3 +405,42 @@ def test_config2_fp32_full(split):
                           oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, G)) <= 1e-5
     assert oracle.rel_err(dA.double().cpu().numpy(),
                           oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, G, b)) <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# two plans on two streams at once (each plan on one stream at a time)
+# ---------------------------------------------------------------------------
+def test_two_plans_on_two_streams_bitwise():
+    print("two plans, two streams", flush=True)
+    a1, b1 = gen.config2(grid=32)                        # stencil, AUTO puts it in the BCSR-part
+    a2 = gen.random_csr(5, 3000, 2500, 0.01)             # scattered, CSR-part
+    b2 = gen.dense(5, gen.DENSE, a2.k, 48)
+    g1 = gen.dense(1, gen.GRAD, a1.m, b1.shape[1])
+    g2 = gen.dense(2, gen.GRAD, a2.m, b2.shape[1])
+    p1 = make_plan(hs, a1, torch.float32, "auto", backward=True)
+    p2 = make_plan(hs, a2, torch.float32, "auto", backward=True)
+    B1, B2, G1, G2 = (to_dev(x, torch.float32) for x in (b1, b2, g1, g2))
+
+    def both(p, B, G):
+        C = p.run(B)
+        dB, dA = p.backward(B, G)
+        return C, dB, dA
+
+    ref1, ref2 = both(p1, B1, G1), both(p2, B2, G2)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    got1, got2 = [], []
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            got1.append(both(p1, B1, G1))
+        with torch.cuda.stream(s2):
+            got2.append(both(p2, B2, G2))
+    torch.cuda.synchronize()
+    for ref, got in ((ref1, got1), (ref2, got2)):
+        for outs in got:
+            for r, g in zip(ref, outs):
+                assert torch.equal(r, g)
+    assert oracle.rel_err(ref1[0].double().cpu().numpy(), oracle_forward(a1, b1)) <= TOL[torch.float32]
+    assert oracle.rel_err(ref2[0].double().cpu().numpy(), oracle_forward(a2, b2)) <= TOL[torch.float32]
