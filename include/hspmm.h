@@ -99,6 +99,11 @@ typedef struct {
     double  plan_ms;              /* wall time of hybrid_spmm_plan */
     int32_t has_backward;
     int64_t t_rows_csr, t_rb_bcsr, t_nblk; /* same split figures for A^T */
+    /* cost-model time of the whole matrix in each part at n_hint, whatever
+     * the split: the inputs of Eq. 1 (BOUNDARY with r_boundary < 0 uses
+     * TP_csr = m / pred_us_csr_all and TP_bcsr = m / pred_us_bcsr_all with
+     * t_csr = t_bcsr = 1) */
+    double  pred_us_csr_all, pred_us_bcsr_all;
 } hspmm_plan_info;
 
 /* Build a plan for A (m x k, nnz entries, CSR) -- Alg. 1 plus the cost model.

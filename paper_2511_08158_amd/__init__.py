@@ -13,6 +13,8 @@ marshalled here, every step of the computation runs in the HIP library
 from __future__ import annotations
 
 import ctypes
+import itertools
+import weakref
 
 import numpy as np
 import torch
@@ -57,6 +59,34 @@ def _out_dtype(compute: int):
     return torch.float64 if compute == _lib.F64 else torch.float32
 
 
+def check_dense(X, rows, cols, dtype, device, name):
+    """Raise HspmmError unless X is a `rows` x `cols` (cols None: any)
+    matrix of `dtype` on `device` with unit column stride, the only form the
+    C ABI can take as a pointer plus a leading dimension."""
+    if not isinstance(X, torch.Tensor):
+        raise HspmmError(-1, f"{name} must be a torch tensor")
+    if X.device != device:
+        raise HspmmError(-1, f"{name} must be on {device}, got {X.device}")
+    if X.dtype != dtype:
+        raise HspmmError(-3, f"{name} must be {dtype}, got {X.dtype}")
+    if X.dim() != 2 or X.shape[0] != rows or (cols is not None and X.shape[1] != cols):
+        want = f"{rows} x {'n' if cols is None else cols}"
+        raise HspmmError(-1, f"{name} must be a {want} matrix, got shape {tuple(X.shape)}")
+    if X.numel() and (X.stride(1) != 1 or X.stride(0) < X.shape[1]):
+        raise HspmmError(-1, f"{name} must be row-major with unit column stride")
+    return X
+
+
+def _ld(X):
+    return X.stride(0) if X.shape[0] > 0 and X.numel() else X.shape[1]
+
+
+# every packing of a plan's values gets a fresh token: the autograd function
+# compares tokens to know whether the plan still holds the values of the
+# forward call it differentiates
+_pack_tokens = itertools.count(1)
+
+
 class Plan:
     """A hybrid plan of a CSR matrix A (m x k) resident on the GPU."""
 
@@ -86,8 +116,23 @@ class Plan:
             _check(L.hybrid_spmm_plan(ctypes.byref(h), m, k, self.nnz_input, _ptr(rp), _ptr(ci),
                                       _ptr(v), DTYPES[v.dtype], ctypes.byref(opts), _stream()))
         self._h = h
-        self._vals_key = (v.data_ptr(), v._version)
+        self._note_packed(vals, v)
         self.backward_enabled = bool(backward)
+
+    def _note_packed(self, vals, v):
+        """Record what the plan now holds: a fresh token, and the caller's
+        tensor (weakly) with its version when the library read that tensor
+        itself rather than a temporary converted copy."""
+        self._pack_token = next(_pack_tokens)
+        same = isinstance(vals, torch.Tensor) and v is vals
+        self._packed_ref = weakref.ref(vals) if same else None
+        self._packed_version = vals._version if same else None
+
+    def holds_values_of(self, vals) -> bool:
+        """True if the last packing read exactly this tensor at its current
+        version (an unchanged static A needs no re-packing)."""
+        r = self._packed_ref
+        return r is not None and r() is vals and self._packed_version == vals._version
 
     # -- lifetime --------------------------------------------------------
     def close(self):
@@ -116,46 +161,43 @@ class Plan:
     def out_dtype(self):
         return _out_dtype(self.compute)
 
-    def _dense(self, X, rows, name):
-        if not X.is_cuda or X.device != self.device:
-            raise HspmmError(-1, f"{name} must be on {self.device}")
-        if X.dtype != self.dense_dtype:
-            raise HspmmError(-3, f"{name} must be {self.dense_dtype}, got {X.dtype}")
-        if X.dim() != 2 or X.shape[0] != rows or X.stride(1) != 1:
-            raise HspmmError(-1, f"{name} must be a row-major {rows} x n matrix")
-        return X
+    def _dense(self, X, rows, name, cols=None, dtype=None):
+        return check_dense(X, rows, cols, self.dense_dtype if dtype is None else dtype, self.device, name)
 
     def run(self, B, out=None):
-        """C = A B; B is k x n (row-major, dtype = compute)."""
+        """C = A B; B is k x n (row-major, dtype = compute); `out`, if
+        given, is an m x n matrix of the output dtype on the plan's device."""
         B = self._dense(B, self.k, "B")
         n = B.shape[1]
         if out is None:
             out = torch.empty((self.m, n), dtype=self.out_dtype, device=self.device)
-        _check(library().hybrid_spmm_run(self.handle, n, _ptr(B), B.stride(0) if self.k else n,
-                                         _ptr(out), out.stride(0) if self.m else n, _stream()))
+        else:
+            self._dense(out, self.m, "out", cols=n, dtype=self.out_dtype)
+        _check(library().hybrid_spmm_run(self.handle, n, _ptr(B), _ld(B), _ptr(out), _ld(out), _stream()))
         return out
 
     def backward(self, B, dC, need_dB=True, need_dA=True):
-        """dB = A^T dC (k x n) and dA[e] = <dC[row(e)], B[col(e)]> in input order."""
+        """dB = A^T dC (k x n) and dA[e] = <dC[row(e)], B[col(e)]> in input
+        order; dC is an m x n matrix of the output dtype on the plan's device."""
         B = self._dense(B, self.k, "B")
         n = B.shape[1]
-        if dC.dtype != self.out_dtype:
-            raise HspmmError(-3, f"dC must be {self.out_dtype}")
-        dC = dC.contiguous()
+        self._dense(dC, self.m, "dC", cols=n, dtype=self.out_dtype)
         dB = torch.empty((self.k, n), dtype=self.out_dtype, device=self.device) if need_dB else None
         dA = torch.empty(self.nnz_input, dtype=self.out_dtype, device=self.device) if need_dA else None
         _check(library().hybrid_spmm_backward(
-            self.handle, n, _ptr(B), B.stride(0) if self.k else n, _ptr(dC), n,
+            self.handle, n, _ptr(B), _ld(B), _ptr(dC), _ld(dC),
             _ptr(dB), n, _ptr(dA), _stream()))
         return dB, dA
 
     def update_values(self, vals):
+        if not isinstance(vals, torch.Tensor):
+            raise HspmmError(-1, "vals must be a torch tensor")
         v = vals if vals.dtype in DTYPES else vals.to(torch.float64)
         v = v.to(self.device).contiguous()
-        if v.numel() != self.nnz_input:
-            raise HspmmError(-1, "vals has the wrong length")
+        if v.dim() != 1 or v.numel() != self.nnz_input:
+            raise HspmmError(-1, "vals must be a vector of nnz entries")
         _check(library().hybrid_spmm_update_values(self.handle, _ptr(v), DTYPES[v.dtype], _stream()))
-        self._vals_key = (vals.data_ptr(), vals._version)
+        self._note_packed(vals, v)
 
     def calibrate(self, B, reps: int = 5) -> dict:
         """Fit the quadratic model (Eq. 2) of forward throughput over
@@ -204,23 +246,32 @@ class Plan:
 class _HybridSpMM(torch.autograd.Function):
     @staticmethod
     def forward(ctx, vals, B, plan):
-        # learnable values change every step: re-pack them; a static A is
-        # packed once at plan time
-        key = (vals.data_ptr(), vals._version)
-        if vals.requires_grad or key != plan._vals_key:
-            plan.update_values(vals.detach())
+        # learnable values change every step and are re-packed; a static A
+        # (the tensor the plan last read, unchanged since) is not
+        if vals.requires_grad or not plan.holds_values_of(vals):
+            plan.update_values(vals)
         C = plan.run(B)
         ctx.plan = plan
-        ctx.save_for_backward(B)
+        ctx.token = plan._pack_token
+        ctx.save_for_backward(vals, B)
         ctx.vals_dtype = vals.dtype
         return C
 
     @staticmethod
     def backward(ctx, dC):
-        (B,) = ctx.saved_tensors
+        vals, B = ctx.saved_tensors
         plan = ctx.plan
         need_dA, need_dB = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        dB, dA = plan.backward(B, dC.to(plan.out_dtype), need_dB=need_dB, need_dA=need_dA)
+        if need_dB and plan._pack_token != ctx.token:
+            # the plan was re-packed since this forward call (another call
+            # with other values, or update_values): dB = A^T dC needs the
+            # values this call multiplied with
+            plan.update_values(vals)
+            ctx.token = plan._pack_token
+        dC = dC.to(plan.out_dtype)
+        if dC.dim() == 2 and dC.numel() and (dC.stride(1) != 1 or dC.stride(0) < dC.shape[1]):
+            dC = dC.contiguous()  # e.g. the broadcast gradient of a sum
+        dB, dA = plan.backward(B, dC, need_dB=need_dB, need_dA=need_dA)
         if dA is not None:
             dA = dA.to(ctx.vals_dtype)
         if dB is not None:

@@ -60,6 +60,7 @@ class PlanInfo(ctypes.Structure):
         ("plan_ms", ctypes.c_double),
         ("has_backward", ctypes.c_int32),
         ("t_rows_csr", ctypes.c_int64), ("t_rb_bcsr", ctypes.c_int64), ("t_nblk", ctypes.c_int64),
+        ("pred_us_csr_all", ctypes.c_double), ("pred_us_bcsr_all", ctypes.c_double),
     ]
 
 

@@ -90,15 +90,44 @@ int hybrid_launch_mode() {
 }
 
 Plan::~Plan() {
+    for (auto& mk : marks) (void)hipEventDestroy(mk.e);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (side) (void)hipStreamDestroy(side);
 }
 
-int ensure_ws(Plan& p, size_t bytes) {
-    if (bytes <= p.ws.bytes) return HSPMM_OK;
-    HIP_TRY(hipDeviceSynchronize());
-    return p.al.alloc(p.ws, bytes);
+int grow_buf(Plan& p, DevBuf& b, size_t bytes) {
+    if (bytes <= b.bytes) return HSPMM_OK;
+    if (b.ptr) p.retired.push_back(std::move(b));
+    return p.al.alloc(b, bytes);
+}
+
+int ensure_ws(Plan& p, size_t bytes) { return grow_buf(p, p.ws, bytes); }
+
+int mark_stream(Plan& p, hipStream_t s) {
+    for (auto& mk : p.marks)
+        if (mk.s == s) {
+            HIP_TRY(hipEventRecord(mk.e, s));
+            return HSPMM_OK;
+        }
+    if (p.marks.size() >= Plan::kMaxMarks) {
+        p.marks_overflow = true;
+        return HSPMM_OK;
+    }
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    p.marks.push_back({s, e});
+    HIP_TRY(hipEventRecord(e, s));
+    return HSPMM_OK;
+}
+
+void wait_plan(Plan& p) {
+    if (p.marks_overflow) {
+        (void)hipDeviceSynchronize();
+        return;
+    }
+    for (auto& mk : p.marks) (void)hipEventSynchronize(mk.e);
+    if (p.side) (void)hipStreamSynchronize(p.side);
 }
 
 }  // namespace hspmm
@@ -183,7 +212,9 @@ int hybrid_spmm_run(hspmm_plan_t h, int64_t n, const void* B, int64_t ldb, void*
     if (!C) return fail(HSPMM_ERR_ARG, "C is NULL");
     if (p.k > 0 && !B) return fail(HSPMM_ERR_ARG, "B is NULL");
     if (ldc < n || (p.k > 0 && ldb < n)) return fail(HSPMM_ERR_ARG, "leading dimension smaller than n");
-    return launch_forward(p, p.A, n, B, ldb, C, ldc, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HSPMM_TRY(launch_forward(p, p.A, n, B, ldb, C, ldc, s));
+    return mark_stream(p, s);
 }
 
 int hybrid_spmm_backward(hspmm_plan_t h, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc,
@@ -221,11 +252,12 @@ int hybrid_spmm_backward(hspmm_plan_t h, int64_t n, const void* B, int64_t ldb, 
         HSPMM_TRY(rc);
         const int rc2 = launch_forward(p, p.T, n, dC, lddc, dB, lddb, s);
         HIP_TRY(hipStreamWaitEvent(s, p.ev_join, 0));
-        return rc2;
+        HSPMM_TRY(rc2);
+        return mark_stream(p, s);
     }
     if (do_dB) HSPMM_TRY(launch_forward(p, p.T, n, dC, lddc, dB, lddb, s));
     if (do_dA) HSPMM_TRY(launch_sddmm(p, n, B, ldb, dC, lddc, dA_vals, s, nullptr));
-    return HSPMM_OK;
+    return mark_stream(p, s);
 }
 
 int hybrid_spmm_update_values(hspmm_plan_t h, const void* vals, int32_t vals_dtype, void* stream) {
@@ -234,7 +266,9 @@ int hybrid_spmm_update_values(hspmm_plan_t h, const void* vals, int32_t vals_dty
     if (!dtype_valid(vals_dtype)) return fail(HSPMM_ERR_DTYPE, "unsupported vals dtype");
     Plan& p = h->p;
     if (p.nnz_in > 0 && !vals) return fail(HSPMM_ERR_ARG, "vals is NULL");
-    return pack_values(p, vals, vals_dtype, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HSPMM_TRY(pack_values(p, vals, vals_dtype, s));
+    return mark_stream(p, s);
 }
 
 int hybrid_spmm_plan_info(hspmm_plan_t h, hspmm_plan_info* info) {
@@ -268,6 +302,8 @@ int hybrid_spmm_plan_info(hspmm_plan_t h, hspmm_plan_info* info) {
     i.t_rows_csr = p.T.rows_csr;
     i.t_rb_bcsr = p.T.rb_bcsr;
     i.t_nblk = p.T.nblk;
+    i.pred_us_csr_all = p.A.pred_all_csr * 1e6;
+    i.pred_us_bcsr_all = p.A.pred_all_bcsr * 1e6;
     *info = i;
     return HSPMM_OK;
 }
@@ -368,7 +404,7 @@ int hybrid_spmm_calibrate(hspmm_plan_t h, int64_t n, const void* B, int64_t ldb,
 
 void hybrid_spmm_destroy(hspmm_plan_t h) {
     if (!h) return;
-    (void)hipDeviceSynchronize();
+    wait_plan(h->p);
     delete h;
 }
 

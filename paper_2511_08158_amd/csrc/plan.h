@@ -17,7 +17,8 @@ struct SubPlan {
 
     std::vector<int32_t> h_rb_nnz, h_rb_nblk;
     std::vector<uint8_t> h_cls;   // 1 = BCSR-part
-    double pred_csr = 0.0, pred_bcsr = 0.0;
+    double pred_csr = 0.0, pred_bcsr = 0.0;       // predicted time of each part of the chosen split
+    double pred_all_csr = 0.0, pred_all_bcsr = 0.0;  // ... of the whole matrix in one part (Eq. 1 inputs)
     int64_t r_boundary = -1;
 
     // CSR-part (Alg. 1 step 1): rows ascending, entries copied
@@ -77,7 +78,21 @@ struct Plan {
 
     DevBuf ws;            // run/backward scratch
     DevBuf ws2;           // scratch of the SDDMM when it runs beside dB
+    // scratch buffers replaced by larger ones: work already queued may still
+    // read them, so they are kept until the plan is destroyed (growth is
+    // geometric and rare: it needs an n beyond every earlier one)
+    std::vector<DevBuf> retired;
     double plan_ms = 0.0;
+
+    // an event recorded after the last call on each stream the plan was used
+    // on: destroy waits for these instead of the whole device
+    struct StreamMark {
+        hipStream_t s;
+        hipEvent_t e;
+    };
+    std::vector<StreamMark> marks;
+    bool marks_overflow = false;  // more streams than kMaxMarks were used
+    static constexpr size_t kMaxMarks = 16;
 
     // side stream of the backward: dA = SDDMM runs on it concurrently with
     // dB = A^T dC, forked from and joined back to the caller's stream by
@@ -103,6 +118,13 @@ int launch_forward(Plan& p, SubPlan& X, int64_t n, const void* B, int64_t ldb, v
 int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dA,
                  hipStream_t s, DevBuf* ws);
 int ensure_ws(Plan& p, size_t bytes);
+// grow `b` to at least `bytes` without waiting for the device: the old
+// buffer goes to p.retired
+int grow_buf(Plan& p, DevBuf& b, size_t bytes);
+// record that work of the plan was queued on stream s
+int mark_stream(Plan& p, hipStream_t s);
+// wait for the plan's queued work (the events of mark_stream)
+void wait_plan(Plan& p);
 
 int calibrate(Plan& p, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc, int reps,
               hspmm_calib_info* info, hipStream_t s);

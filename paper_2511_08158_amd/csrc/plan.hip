@@ -461,6 +461,13 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
     double t_c = 0, t_b = 0;
     choose_auto(p.mm, X.h_rb_nnz, X.h_rb_nblk, nh, sv, sb, br, X.kc, auto_cls, t_c, t_b);
     X.h_cls.assign(nrb, 0);
+    // the whole matrix in either part: the aggregate throughputs of Eq. 1
+    X.pred_all_csr = X.pred_all_bcsr = 0;
+    for (int64_t q = 0; q < nrb; ++q) {
+        RowBlockCost c = rowblock_cost(p.mm, X.h_rb_nnz[q], X.h_rb_nblk[q], nh, sv, sb, br, X.kc);
+        X.pred_all_csr += c.t_csr;
+        X.pred_all_bcsr += c.t_bcsr;
+    }
     if (split == HSPMM_SPLIT_AUTO) {
         X.h_cls = auto_cls;
     } else if (split == HSPMM_SPLIT_BCSR_ONLY) {
@@ -470,14 +477,8 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
         if (&X == &p.T || rbd < 0) {
             // Eq. 1: the aggregate throughput of each part is m / (its
             // predicted time for the whole matrix)
-            double all_c = 0, all_b = 0;
-            for (int64_t q = 0; q < nrb; ++q) {
-                RowBlockCost c = rowblock_cost(p.mm, X.h_rb_nnz[q], X.h_rb_nblk[q], nh, sv, sb, br, X.kc);
-                all_c += c.t_csr;
-                all_b += c.t_bcsr;
-            }
-            const double tpc = all_c > 0 ? (double)m / all_c : 1.0;
-            const double tpb = all_b > 0 ? (double)m / all_b : 1.0;
+            const double tpc = X.pred_all_csr > 0 ? (double)m / X.pred_all_csr : 1.0;
+            const double tpb = X.pred_all_bcsr > 0 ? (double)m / X.pred_all_bcsr : 1.0;
             rbd = eq1_boundary(m, tpc, 1.0, tpb, 1.0, br);
         }
         if (rbd > m) rbd = m;

@@ -7,6 +7,7 @@
 // of 16 tiles at a time is one 16 x 16 MFMA product (K = the n columns);
 // only the slots that hold an entry of A are written.
 #include "plan.h"
+#include "prim.h"
 
 namespace hspmm {
 
@@ -370,9 +371,13 @@ __device__ void sdd_bcsr_wg_h(const SddArgs& a, int64_t slot, unsigned char* sme
     if (lane == 0) red[w] = mx;
     __syncthreads();
     mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    // mx in [2^(e-1), 2^e); a zero or non-finite slab is left unscaled
+    // mx in [2^(e-1), 2^e); a zero or non-finite slab is left unscaled.
+    // e is held at -111 or above so that both 2^(15 - e) and 2^(e - 15)
+    // are finite normal FP32 numbers: a slab below 2^-112 is scaled by
+    // 2^126 only (its largest magnitude then stays below 2^14)
     int e = 0;
     (void)frexpf(mx, &e);
+    e = e < -111 ? -111 : e;
     const bool scl = mx > 0.f && mx <= 3.4e38f;
     const float s = scl ? ldexpf(1.f, e - 15) : 1.f;
     const float inv = scl ? ldexpf(1.f, 15 - e) : 1.f;
@@ -522,14 +527,13 @@ int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC,
     void* target = dA;
     DevBuf& ws = wsb ? *wsb : p.ws;
     if (!p.canonical) {
-        if (ws.bytes < (size_t)p.nnz * go) {
-            HIP_TRY(hipDeviceSynchronize());
-            HSPMM_TRY(p.al.alloc(ws, (size_t)p.nnz * go));
-        }
+        HSPMM_TRY(grow_buf(p, ws, (size_t)p.nnz * go));
         target = ws.ptr;
     }
     if (n == 0) {
-        HIP_TRY(hipMemsetAsync(target, 0, (size_t)p.nnz * go, s));
+        // a fill kernel rather than a memset node (callers may capture the
+        // backward in a graph); 0.0 is the all-zero bit pattern in FP32/FP64
+        HSPMM_TRY(fill_i32(static_cast<int32_t*>(target), 0, p.nnz * (int64_t)(go / 4), s));
     } else {
         SddArgs a{X.vr_start.as<int32_t>(), X.vr_end.as<int32_t>(), X.vr_row.as<int32_t>(), X.csr_col.as<int32_t>(),
                   X.csr_src.as<int32_t>(), X.n_vrows, X.bcsr_rb.as<int32_t>(), X.blk_ptr.as<int32_t>(),

@@ -596,7 +596,10 @@ __device__ void bcsr_wave_h(const BcsrArgs& a, const DenseArgs& d, int64_t unit)
     for (int t = 0; t < CPL; ++t) acc[t] = f4_t{0.f, 0.f, 0.f, 0.f};
     const int nsteps = (cnt + 31) >> 5;
     HStep<T, CPL> x, y;
-    load_hstep<T, CPL>(a, vals, B, d.ldb, b0, cnt, 0, lane, g, col, x);
+    // an empty row block (forced splits put them in the BCSR-part) has no
+    // packed values at all: its first step must not be loaded, since
+    // blk_ptr of the last row block can be the end of the value array
+    if (nsteps > 0) load_hstep<T, CPL>(a, vals, B, d.ldb, b0, cnt, 0, lane, g, col, x);
     for (int s = 0; s < nsteps; s += 2) {
         // the step after the last one reloads the last (multiplied by zero)
         const int s1 = min(s + 1, nsteps - 1), s2 = min(s + 2, nsteps - 1);

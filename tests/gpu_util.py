@@ -31,16 +31,17 @@ def quantized_dense(B, dtype):
 def rounded_slabs(G, row_blocks, dtype=torch.float16):
     """dC as the FP16/BF16 SDDMM's matrix-core form reads it: each listed
     16-row block scaled by the power of two 2^(e-15) that puts its largest
-    magnitude in [2^14, 2^15), rounded to `dtype` (nearest even) and scaled
-    back; other rows unchanged."""
+    magnitude in [2^14, 2^15) (e held at -111 or above, so a slab below
+    2^-112 is scaled by 2^126 only), rounded to `dtype` (nearest even) and
+    scaled back; other rows unchanged."""
     out = np.array(G, dtype=np.float64, copy=True)
     for rb in np.asarray(row_blocks):
         sl = slice(16 * int(rb), min(16 * int(rb) + 16, out.shape[0]))
         mx = float(np.max(np.abs(out[sl]))) if out[sl].size else 0.0
         if mx == 0.0 or not np.isfinite(mx):
             continue
-        e = np.frexp(mx)[1]
-        s = np.ldexp(1.0, int(e) - 15)
+        e = max(int(np.frexp(np.float32(mx))[1]), -111)
+        s = np.ldexp(1.0, e - 15)
         q = torch.as_tensor(out[sl] / s).to(torch.float32).to(dtype).to(torch.float64).numpy()
         out[sl] = q * s
     return out

@@ -78,3 +78,29 @@ def test_struct_sizes_match_header():
     assert got == [ctypes.sizeof(_lib.PlanOpts), ctypes.sizeof(_lib.PlanInfo),
                    _lib.PlanOpts.max_workspace_bytes.offset, _lib.PlanInfo.plan_ms.offset,
                    _lib.PlanInfo.t_nblk.offset, ctypes.sizeof(_lib.CalibInfo), _lib.CalibInfo.applied.offset]
+
+
+def test_binding_operand_checks_on_the_host():
+    """The binding rejects a dense operand of the wrong device, dtype, shape
+    or layout before any pointer reaches the C ABI (host tensors stand in
+    for device ones: the check compares devices, no GPU is touched)."""
+    import torch
+
+    import paper_2511_08158_amd as hs
+    cpu = torch.device("cpu")
+    ok = torch.zeros((5, 3))
+    assert hs.check_dense(ok, 5, 3, torch.float32, cpu, "X") is ok
+    assert hs.check_dense(torch.zeros((8, 6))[:, :3], 8, None, torch.float32, cpu, "X") is not None
+    bad = [
+        (ok, 5, 3, torch.float32, torch.device("cuda:0")),          # device
+        (ok, 5, 3, torch.float64, cpu),                             # dtype
+        (ok, 4, 3, torch.float32, cpu),                             # rows
+        (ok, 5, 4, torch.float32, cpu),                             # columns
+        (torch.zeros((3, 5)).t(), 5, 3, torch.float32, cpu),        # column-major
+        (torch.zeros(15), 5, 3, torch.float32, cpu),                # not a matrix
+        (torch.zeros((1, 3)).expand(5, 3), 5, 3, torch.float32, cpu),  # rows overlap
+        (ok.numpy(), 5, 3, torch.float32, cpu),                     # not a tensor
+    ]
+    for X, r, c, dt, dv in bad:
+        with pytest.raises(hs.HspmmError):
+            hs.check_dense(X, r, c, dt, dv, "X")

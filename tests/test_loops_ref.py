@@ -148,6 +148,37 @@ def test_argmax_matches_concave_closed_form():
     assert L.argmax_ref(coef, 4) == best == (1, 3)
 
 
+def test_argmax_box_bounds():
+    """Pin of the box-bounded form (x_min <= x <= x_max, y_min <= y <= y_max
+    beside x + y <= T): for the separable concave quadratic with its free
+    optimum (3, 5) outside the box [0, 2] x [0, 4] and T large enough that
+    the triangle does not bind, each coordinate is maximised at its nearest
+    box edge, the corner (2, 4); with lower bounds above the optimum the
+    opposite corner (x_min, y_min) wins; and over random concave and convex
+    quadratics, boxes and T the result equals an independent brute force
+    that ranks candidates by value, then by (x, y)."""
+    coef = np.array([0.0, 6.0, 10.0, -1.0, -1.0])   # free optimum (3, 5)
+    assert L.argmax_ref(coef, 100, x_max=2, y_max=4) == (2, 4)
+    assert L.argmax_ref(coef, 100, x_min=5, y_min=7, x_max=9, y_max=9) == (5, 7)
+    # T binding inside the box: x + y <= 5 within [0, 2] x [0, 4]
+    # maximise 6x - x^2 + 10y - y^2 on x + y <= 5: (1, 4) gives 5 + 24 = 29,
+    # (2, 3) gives 8 + 21 = 29, the tie goes to the smaller x
+    assert L.argmax_ref(coef, 5, x_max=2, y_max=4) == (1, 4)
+    g = np.random.default_rng(17)
+    for _ in range(200):
+        c = g.normal(size=5) * np.array([1.0, 4.0, 4.0, 1.0, 1.0])
+        T = int(g.integers(1, 12))
+        x0, y0 = int(g.integers(0, 4)), int(g.integers(0, 4))
+        x1, y1 = x0 + int(g.integers(0, 6)), y0 + int(g.integers(0, 6))
+        cand = [(x, y) for x in range(x0, x1 + 1) for y in range(y0, y1 + 1) if 1 <= x + y <= T]
+        want = None
+        if cand:
+            vals = [c[0] + c[1] * x + c[2] * y + c[3] * x * x + c[4] * y * y for x, y in cand]
+            top = max(vals)
+            want = min(p for p, v in zip(cand, vals) if v == top)
+        assert L.argmax_ref(c, T, x_min=x0, y_min=y0, x_max=x1, y_max=y1) == want
+
+
 # ---------------------------------------------------------------------------
 # FP16 / BF16 rounding and per-row-block scaling
 # ---------------------------------------------------------------------------
