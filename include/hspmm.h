@@ -131,6 +131,24 @@ int hybrid_spmm_plan(hspmm_plan_t* out, int64_t m, int64_t k, int64_t nnz,
 int hybrid_spmm_run(hspmm_plan_t p, int64_t n, const void* B, int64_t ldb,
                     void* C, int64_t ldc, void* stream);
 
+/* The same product as hybrid_spmm_run for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): nothing is allocated, on the host or the
+ * device.  The partial rows of split CSR rows go to a static device array
+ * of HSPMM_NOALLOC_SCRATCH_BYTES bytes per GPU, held from the library's
+ * first use of it on that GPU until the process ends, instead of the plan's
+ * growable buffer.  Arguments, layout and results are those of
+ * hybrid_spmm_run (bitwise: the same kernels); C is overwritten.
+ * Every call on one GPU shares that GPU's array, so calls that overlap on
+ * one GPU (other streams, other plans, other threads) race: order them.
+ * The array needs no clearing: each call writes every slot it reads.
+ * Errors: ARG; OOM when the split rows need more than the static array at
+ * this n (n_partials * n * 4 bytes, 8 for F64 plans; nothing is launched);
+ * HIP. */
+#define HSPMM_NOALLOC_SCRATCH_BYTES 33554432u /* 32 MiB */
+int hybrid_spmm_run_noalloc(hspmm_plan_t p, int64_t n, const void* B, int64_t ldb,
+                            void* C, int64_t ldc, void* stream);
+
 /* Gradients of L(vals, B) through C = A * B, given dC = dL/dC:
  *   dB = A^T * dC  (k x n, ld lddb; FP64 for F64 plans, FP32 otherwise), or
  *        skipped if dB is NULL;

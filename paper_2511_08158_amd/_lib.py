@@ -87,7 +87,7 @@ class CalibInfo(ctypes.Structure):
 EXPORTED = [
     "hybrid_spmm_plan", "hybrid_spmm_run", "hybrid_spmm_backward", "hybrid_spmm_update_values",
     "hybrid_spmm_plan_info", "hybrid_spmm_export", "hybrid_spmm_destroy",
-    "hybrid_spmm_last_error", "hybrid_spmm_version", "hybrid_spmm_calibrate",
+    "hybrid_spmm_last_error", "hybrid_spmm_version", "hybrid_spmm_calibrate", "hybrid_spmm_run_noalloc",
 ]
 
 _lib = None
@@ -105,6 +105,7 @@ def load():
     L.hybrid_spmm_plan.argtypes = [ctypes.POINTER(vp), i64, i64, i64, vp, vp, vp, i32,
                                    ctypes.POINTER(PlanOpts), vp]
     L.hybrid_spmm_run.argtypes = [vp, i64, vp, i64, vp, i64, vp]
+    L.hybrid_spmm_run_noalloc.argtypes = [vp, i64, vp, i64, vp, i64, vp]
     L.hybrid_spmm_backward.argtypes = [vp, i64, vp, i64, vp, i64, vp, i64, vp, vp]
     L.hybrid_spmm_update_values.argtypes = [vp, vp, i32, vp]
     L.hybrid_spmm_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
@@ -112,7 +113,7 @@ def load():
     L.hybrid_spmm_calibrate.argtypes = [vp, i64, vp, i64, vp, i64, i32, ctypes.POINTER(CalibInfo), vp]
     L.hybrid_spmm_destroy.argtypes = [vp]
     L.hybrid_spmm_destroy.restype = None
-    for f in (L.hybrid_spmm_plan, L.hybrid_spmm_run, L.hybrid_spmm_backward,
+    for f in (L.hybrid_spmm_plan, L.hybrid_spmm_run, L.hybrid_spmm_run_noalloc, L.hybrid_spmm_backward,
               L.hybrid_spmm_update_values, L.hybrid_spmm_plan_info, L.hybrid_spmm_export,
               L.hybrid_spmm_calibrate):
         f.restype = ctypes.c_int

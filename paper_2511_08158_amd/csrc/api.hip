@@ -6,10 +6,6 @@
 
 #include "plan.h"
 
-struct hspmm_plan {
-    hspmm::Plan p;
-};
-
 namespace hspmm {
 
 namespace {
@@ -119,6 +115,15 @@ int mark_stream(Plan& p, hipStream_t s) {
     p.marks.push_back({s, e});
     HIP_TRY(hipEventRecord(e, s));
     return HSPMM_OK;
+}
+
+void mark_stream_noalloc(Plan& p, hipStream_t s) {
+    for (auto& mk : p.marks)
+        if (mk.s == s) {
+            if (hipEventRecord(mk.e, s) != hipSuccess) p.marks_overflow = true;
+            return;
+        }
+    p.marks_overflow = true;
 }
 
 void wait_plan(Plan& p) {

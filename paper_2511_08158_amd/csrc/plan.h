@@ -111,9 +111,22 @@ struct LaunchQuery {
     int wg_per_cu = 0;               // resident workgroups per CU for the kernel
 };
 
+// A caller-provided scratch buffer for the partial rows of split CSR rows
+// (used instead of the plan's own, which may grow): device pointer and
+// capacity in bytes; a launch needing more fails with HSPMM_ERR_OOM.
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
 // forward product of one sub-plan: C = X * B
 int launch_forward(Plan& p, SubPlan& X, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc,
-                   hipStream_t s, LaunchQuery* q = nullptr);
+                   hipStream_t s, LaunchQuery* q = nullptr, const Workspace* ext = nullptr);
+// bytes of split-row scratch a forward product of X at width n needs
+size_t forward_scratch_bytes(const SubPlan& X, int64_t n);
+// like mark_stream, but never creates an event: a stream without one makes
+// destroy wait for the whole device instead
+void mark_stream_noalloc(Plan& p, hipStream_t s);
 // SDDMM on A's pattern: dA_canon[c] (or dA_in[e] via canon_of_orig)
 int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dA,
                  hipStream_t s, DevBuf* ws);
@@ -133,3 +146,8 @@ int build_plan(Plan& p, const int32_t* row_ptr, const int32_t* col_idx, const vo
                hipStream_t s);
 
 }  // namespace hspmm
+
+// the opaque handle of the C ABI
+struct hspmm_plan {
+    hspmm::Plan p;
+};

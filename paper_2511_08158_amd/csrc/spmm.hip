@@ -967,20 +967,36 @@ int dispatch_half(const SubPlan& X, const DenseArgs& d, bool vec_ok, hipStream_t
 
 }  // namespace
 
+size_t forward_scratch_bytes(const SubPlan& X, int64_t n) {
+    const size_t acc_b = X.ct == HSPMM_F64 ? 8 : 4;
+    return (size_t)X.n_partials * (size_t)n * acc_b;
+}
+
 int launch_forward(Plan& p, SubPlan& X, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc,
-                   hipStream_t s, LaunchQuery* q) {
+                   hipStream_t s, LaunchQuery* q, const Workspace* ext) {
     if (X.m == 0 || n == 0) {
         if (q) *q = LaunchQuery{};
         return HSPMM_OK;
     }
     const size_t eb = dtype_size(X.ct);
     const size_t ec = dtype_size(out_dtype(X.ct));
-    // partial rows of split CSR rows
+    // partial rows of split CSR rows: every slot is written by its segment
+    // before the reduction reads it, so the scratch needs no clearing
+    void* ws = nullptr;
     if (X.n_partials > 0) {
-        const size_t acc_b = X.ct == HSPMM_F64 ? 8 : 4;
-        HSPMM_TRY(ensure_ws(p, (size_t)X.n_partials * (size_t)n * acc_b));
+        const size_t need = forward_scratch_bytes(X, n);
+        if (ext) {
+            if (need > ext->bytes)
+                return fail(HSPMM_ERR_OOM, "split rows need " + std::to_string(need) +
+                                               " bytes of scratch at this n; the static scratch holds " +
+                                               std::to_string(ext->bytes));
+            ws = ext->ptr;
+        } else {
+            HSPMM_TRY(ensure_ws(p, need));
+            ws = p.ws.ptr;
+        }
     }
-    DenseArgs d{B, ldb, C, ldc, n, X.m, p.ws.ptr, X.scaled ? X.scale.as<double>() : nullptr};
+    DenseArgs d{B, ldb, C, ldc, n, X.m, ws, X.scaled ? X.scale.as<double>() : nullptr};
     const int vec_elems = (int)(16 / eb);
     // every lane must be able to issue full 16-byte loads of B and the
     // matching stores of C
