@@ -17,6 +17,14 @@ the launch stream), and the CPU baseline: the FP64 oracle timed on the host
 cores, whose outputs of the same step are also the references of the
 error of every GPU output (without the CPU baseline, the errors are null).
 The oracle runs in that leg only.
+
+Timing protocol of the graded figures: every timed step is cold -- a 1 GiB
+fill between steps, outside the events, evicts the inputs, the plan and the
+outputs from L2 and the 256 MB MALL (the block stencil's 87 MB per product
+would otherwise be served from the MALL).  `value` and `ms_per_step` are the
+median over the K timed steps; the roofline entry uses the dominant kernel's
+mean duration inside those cold steps.  Warm (back-to-back) figures are
+reported beside them.
 """
 from __future__ import annotations
 
@@ -64,7 +72,32 @@ def parse():
     ap.add_argument("--no-vendor", action="store_true", help="skip the vendor CSR product timed for context")
     ap.add_argument("--no-other-dtypes", action="store_true",
                     help="skip the same step in the other compute precisions (stencil only)")
+    ap.add_argument("--graded-only", action="store_true",
+                    help="only the W warm-up and K timed cold steps of the hybrid plan (for profiling)")
     return ap.parse_args()
+
+
+# The paper's own figures (Apple M4 Pro CPU, SuiteSparse matrices, N = 32,
+# forward only; Sec. 4.2 and Table 3), quoted beside the bench line as
+# context: other hardware, other matrices, other width.
+PAPER_CONTEXT = {
+    "hardware": "Apple M4 Pro CPU (12 cores, 2 SME units)",
+    "n": 32, "pass": "forward only", "matrices": "SuiteSparse (absent here)",
+    "fp16_best_matrix_gflops": 1964.9,
+    "table3_fp16_gflops_range": [70, 1042],
+    "hybrid_vs_csr_only_avg_speedup": 45.64,
+    "hybrid_best_share_of_matrices": 0.833,
+}
+
+
+def cpu_model() -> str:
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def sweep(args):
@@ -380,11 +413,46 @@ def main():
         return out
 
     flush_buf = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+    kernel_names = ("forward", "backward_dB", "backward_dA")
+
+    def cold_steps(plan, steps, warmup, per_kernel):
+        """`warmup` untimed and `steps` timed cold steps.  Before each step a
+        1 GiB fill (outside the events) evicts the inputs, the plan and the
+        outputs from L2 and the 256 MB MALL.  HIP events on the launch stream
+        bracket the step (per_kernel: each of its three launches, which
+        costs each launch a few microseconds of event processing).  Returns
+        the per-step (and per-launch) durations in us."""
+        C = torch.empty((a.m, n), dtype=torch.float32, device=dev)
+
+        def one(i):
+            flush_buf.fill_(float(i))
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4 if per_kernel else 2)]
+            ev[0].record(stream)
+            plan.run(B, out=C)
+            if per_kernel:
+                ev[1].record(stream)
+                plan.backward(B, dC, need_dB=True, need_dA=False)
+                ev[2].record(stream)
+                plan.backward(B, dC, need_dB=False, need_dA=True)
+            else:
+                plan.backward(B, dC)
+            ev[-1].record(stream)
+            return ev
+
+        for i in range(warmup):
+            one(i)
+        torch.cuda.synchronize()
+        evs = [one(warmup + i) for i in range(steps)]
+        torch.cuda.synchronize()
+        out = {"step_us": np.array([ev[0].elapsed_time(ev[-1]) * 1e3 for ev in evs])}
+        if per_kernel:
+            out["kernels"] = {name: np.array([ev[j].elapsed_time(ev[j + 1]) * 1e3 for ev in evs])
+                              for j, name in enumerate(kernel_names)}
+        return out
 
     def step_percentiles(plan, reps, cold):
         """Per-step durations (HIP events around each step on the launch
-        stream); cold: a 1 GiB fill between steps, outside the events, evicts
-        the inputs from L2 and the 256 MB MALL."""
+        stream); cold: a 1 GiB fill between steps, outside the events."""
         C = torch.empty((a.m, n), dtype=torch.float32, device=dev)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for i in range(reps + 2):
@@ -398,17 +466,49 @@ def main():
                 ev[i - 2][1].record(stream)
         torch.cuda.synchronize()
         us = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev])
+        return pct(us)
+
+    def pct(us):
         return {q: float(np.percentile(us, p)) for q, p in (("p10", 10), ("p50", 50), ("p90", 90))}
+
+    flops = 6.0 * a.nnz * n
+    sv = sb = 4 if dt == "f32" else 2
+    per_launch = {
+        "forward": alg_bytes_forward(a.m, a.k, a.nnz, n, sv, sb, 4),
+        "backward_dB": alg_bytes_forward(a.k, a.m, a.nnz, n, 4, 4, 4),
+        "backward_dA": alg_bytes_sddmm(a.m, a.k, a.nnz, n, sb, 4, 4),
+    }
+    step_bytes = sum(per_launch.values())
+
+    if args.graded_only:
+        # the graded measurement alone (the profiled command): W warm-up and
+        # K timed cold steps of the hybrid plan
+        plan, _ = make("auto")
+        cs = cold_steps(plan, args.steps, args.warmup, per_kernel=True)
+        t = float(np.median(cs["step_us"])) * 1e-6
+        print(json.dumps({"graded_only": True, "workload": wname, "steps": args.steps, "warmup": args.warmup,
+                          "value": round(flops / t / 1e9, 2), "ms_per_step": round(t * 1e3, 5),
+                          "kernels_us_cold_mean": {k: round(float(v.mean()), 2) for k, v in cs["kernels"].items()}}),
+              flush=True)
+        return
 
     results = {}
     for split in ("auto", "csr"):
         plan, plan_ms = make(split)
-        t = time_steps(plan, args.steps, args.warmup)
-        kt = time_kernels(plan, max(10, args.steps))
-        reps_p = max(10, min(100, args.steps))
-        results[split] = {"plan": plan, "t": t, "plan_ms": plan_ms, "kernels_us": kt,
-                          "info": plan.info(), "warm": step_percentiles(plan, reps_p, False),
-                          "cold": step_percentiles(plan, reps_p, True)}
+        t_warm = time_steps(plan, args.steps, args.warmup)
+        kt_warm = time_kernels(plan, max(10, args.steps))
+        # the graded timed region: exactly K cold steps, one event pair each
+        torch.cuda.synchronize()
+        cs = cold_steps(plan, args.steps, args.warmup, per_kernel=False)
+        torch.cuda.synchronize()
+        # per-launch durations for the roofline: the same cold steps with
+        # events between the launches
+        ck = cold_steps(plan, args.steps, 2, per_kernel=True)
+        reps_p = max(100, args.steps)
+        results[split] = {"plan": plan, "t_warm": t_warm, "plan_ms": plan_ms, "kernels_us_warm": kt_warm,
+                          "cold": cs, "cold_k": ck, "t": float(np.median(cs["step_us"])) * 1e-6,
+                          "info": plan.info(), "pct_warm": step_percentiles(plan, reps_p, False),
+                          "pct_cold": step_percentiles(plan, reps_p, True)}
     del flush_buf
 
     # CPU baseline (the only leg that runs the oracle): whole fwd+bwd passes
@@ -420,26 +520,32 @@ def main():
     refs = refs0 = cpu_line = None
     if not args.no_cpu_baseline:
         import oracle as orc
-        threads = min(len(os.sched_getaffinity(0)), 16)
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            r_c = orc.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, b_used, nthreads=threads)
-            r_db = orc.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, g, nthreads=threads)
-            r_da = orc.sddmm(a.m, a.k, a.row_ptr, a.col_idx, g, b_used, nthreads=threads)
-            reps += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds or reps >= 50:
-                break
-        tc = (time.perf_counter() - t0) / reps
+        # the host's share of cores on the GPU machine is 16 threads whatever
+        # the affinity mask shows; the threads used are reported as `cores`
+        visible = len(os.sched_getaffinity(0))
+        threads = min(visible, 16)
+
+        def oracle_pass(nt):
+            t0 = time.perf_counter()
+            r = (orc.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, b_used, nthreads=nt),
+                 orc.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, g, nthreads=nt),
+                 orc.sddmm(a.m, a.k, a.row_ptr, a.col_idx, g, b_used, nthreads=nt))
+            return time.perf_counter() - t0, r
+
+        oracle_pass(threads)  # warm-up
+        times, t_start = [], time.perf_counter()
+        while len(times) < 3 or (time.perf_counter() - t_start < args.cpu_seconds and len(times) < 50):
+            dt_pass, (r_c, r_db, r_da) = oracle_pass(threads)
+            times.append(dt_pass)
+        tc = float(np.median(times))
         cpu_line = {"value": round(6.0 * a.nnz * n / tc / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
                     "kind": "oracle",
-                    "sample": f"{reps} full fwd+bwd passes of the FP64 oracle on the same workload"}
+                    "sample": f"median of {len(times)} full fwd+bwd passes (C, dB, dA) of the FP64 oracle on the "
+                              f"whole workload after one warm-up pass",
+                    "host_cores_visible": visible, "cpu_model": cpu_model()}
         # one single-threaded pass beside it (the oracle sums each row in
         # order whatever the thread count, so the outputs are the same)
-        t1 = time.perf_counter()
-        orc.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, b_used, nthreads=1)
-        orc.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, g, nthreads=1)
-        orc.sddmm(a.m, a.k, a.row_ptr, a.col_idx, g, b_used, nthreads=1)
-        cpu_line["single_thread_value"] = round(6.0 * a.nnz * n / (time.perf_counter() - t1) / 1e9, 3)
+        cpu_line["single_thread_value"] = round(6.0 * a.nnz * n / oracle_pass(1)[0] / 1e9, 3)
         refs = {"C": r_c, "dB": r_db, "dA": r_da}
         # the unquantised problem: end-to-end reference of the other precisions
         if dt == "f32" and np.array_equal(b_used, b):
@@ -458,27 +564,23 @@ def main():
                "dA": rel_err(dA.double().cpu().numpy(), refs["dA"])}
     tol = 1e-5 if dt == "f32" else 5e-3
 
-    flops = 6.0 * a.nnz * n
     t_h, t_c = results["auto"]["t"], results["csr"]["t"]
     gflops = flops / t_h / 1e9
 
-    # roofline of the dominant kernel of the hybrid step
-    sv = sb = 4 if dt == "f32" else 2
-    per_launch = {
-        "forward": alg_bytes_forward(a.m, a.k, a.nnz, n, sv, sb, 4),
-        "backward_dB": alg_bytes_forward(a.k, a.m, a.nnz, n, 4, 4, 4),
-        "backward_dA": alg_bytes_sddmm(a.m, a.k, a.nnz, n, sb, 4, 4),
-    }
-    kt = results["auto"]["kernels_us"]
-    dom = max(kt, key=kt.get)
-    achieved = per_launch[dom] / (kt[dom] * 1e-6) / 1e9
+    # roofline of the dominant kernel of the hybrid step: mean duration of
+    # each launch inside the timed cold steps
+    kc = {k: float(v.mean()) for k, v in results["auto"]["cold_k"]["kernels"].items()}
+    dom = max(kc, key=kc.get)
+    achieved = per_launch[dom] / (kc[dom] * 1e-6) / 1e9
     traffic = None
     prof = ROOT / "profiles" / f"traffic_{wname}.json"
     if prof.exists():
         rec = json.loads(prof.read_text())
         if rec.get("sources_hash") == kernel_sources_hash():
             traffic = rec.get("bytes_per_launch", {}).get(dom)
-    step_bytes = sum(per_launch.values())
+
+    def rnd(d):
+        return {k: round(v, 2) for k, v in d.items()}
 
     line = {
         "metric": "SpMM GFLOP/s & % HBM roofline, hybrid vs CSR-only, fwd+bwd, at stated error",
@@ -494,25 +596,36 @@ def main():
         "dtype": dt,
         "data": "synthetic",
         "config": {"workload": wname, "m": a.m, "k": a.k, "nnz": a.nnz, "n": n,
-                   "step": "C=A*B; dB=A^T*dC; dA=SDDMM(dC,B)", "split": "auto"},
+                   "step": "C=A*B; dB=A^T*dC; dA=SDDMM(dC,B)", "split": "auto",
+                   "timing": "cold: 1 GiB fill between steps outside the events; median of the K timed steps"},
         "hbm_roofline_frac_step": round(step_bytes / t_h / (HBM_PEAK_GBS * 1e9), 4),
         "csr_only": {"value": round(flops / t_c / 1e9, 2), "ms_per_step": round(t_c * 1e3, 5),
-                     "kernels_us": {k: round(v, 2) for k, v in results["csr"]["kernels_us"].items()}},
+                     "kernels_us_cold_mean": rnd({k: float(v.mean()) for k, v in results["csr"]["cold_k"]["kernels"].items()}),
+                     "kernels_us_warm": rnd(results["csr"]["kernels_us_warm"])},
         "speedup_vs_csr_only": round(t_c / t_h, 3),
+        "warm": {"value": round(flops / results["auto"]["t_warm"] / 1e9, 2),
+                 "ms_per_step": round(results["auto"]["t_warm"] * 1e3, 5),
+                 "csr_only_value": round(flops / results["csr"]["t_warm"] / 1e9, 2),
+                 "hbm_roofline_frac_step": round(step_bytes / results["auto"]["t_warm"] / (HBM_PEAK_GBS * 1e9), 4),
+                 "kernels_us": rnd(results["auto"]["kernels_us_warm"])},
         "step_us_percentiles": {
-            mode: {"auto": {k: round(v, 2) for k, v in results["auto"][mode].items()},
-                   "csr_only": {k: round(v, 2) for k, v in results["csr"][mode].items()},
-                   "gflops_p50": round(flops / (results["auto"][mode]["p50"] * 1e-6) / 1e9, 1),
-                   "speedup_vs_csr_only_p50": round(results["csr"][mode]["p50"] / results["auto"][mode]["p50"], 3)}
+            mode: {"steps": max(100, args.steps),
+                   "auto": rnd(results["auto"][f"pct_{mode}"]),
+                   "csr_only": rnd(results["csr"][f"pct_{mode}"]),
+                   "gflops_p50": round(flops / (results["auto"][f"pct_{mode}"]["p50"] * 1e-6) / 1e9, 1),
+                   "speedup_vs_csr_only_p50": round(results["csr"][f"pct_{mode}"]["p50"] / results["auto"][f"pct_{mode}"]["p50"], 3)}
             for mode in ("warm", "cold")},
+        "timed_steps_us": rnd(pct(results["auto"]["cold"]["step_us"])),
         "error": None if err is None else {k: float(f"{v:.3e}") for k, v in err.items()},
         "error_ok": None if err is None else all(v <= tol for v in err.values()),
-        "kernels_us": {k: round(v, 2) for k, v in kt.items()},
+        "kernels_us": rnd(kc),
         "plan_ms": round(results["auto"]["plan_ms"], 1),
         "split": {k: results["auto"]["info"][k] for k in ("rows_csr", "rb_bcsr", "nblk", "fill")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "alg_bytes_per_launch": per_launch[dom]},
+                     "traffic": traffic, "alg_bytes_per_launch": per_launch[dom],
+                     "timing": "mean launch duration in K cold steps with events between the launches"},
+        "context": PAPER_CONTEXT,
     }
 
     if not args.no_vendor:
@@ -538,7 +651,7 @@ def main():
             line["vendor_csr_forward"] = {
                 "library": "torch.sparse CSR @ dense (hipSPARSE)", "us": round(tv, 2),
                 "gflops": round(2.0 * a.nnz * n / (tv * 1e-6) / 1e9, 1),
-                "hybrid_forward_speedup": round(tv / kt["forward"], 3),
+                "hybrid_forward_speedup_warm": round(tv / results["auto"]["kernels_us_warm"]["forward"], 3),
                 "agreement_rel_err": float(f"{rel_err(Cv.double().cpu().numpy(), Ch.double().cpu().numpy()):.2e}")}
             del Av, Cv
         except Exception as ex:  # the vendor path is optional context
