@@ -66,3 +66,41 @@ def oracle_forward(a, B):
 def make_plan(hs, a, dtype, split="auto", backward=False, vals_dtype=torch.float64, **kw):
     return hs.Plan(a.row_ptr, a.col_idx, to_dev(a.vals, vals_dtype), (a.m, a.k), compute=dtype,
                    split=split, backward=backward, **kw)
+
+
+def scaled_row_errors(X, ref, absref):
+    """Per-row error of X against ref, each row measured against the row of
+    |A| |B| (absref, the scale any rounding error of that row is bounded
+    by): ||X_i - ref_i|| / ||absref_i|| (rows whose absref is zero must
+    match exactly and count 0 if they do, inf otherwise).  Unlike a norm over
+    the whole matrix, one wrong row cannot hide among many right ones."""
+    X = np.asarray(X, dtype=np.float64).reshape(len(ref), -1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(len(ref), -1)
+    absref = np.asarray(absref, dtype=np.float64).reshape(len(ref), -1)
+    num = np.linalg.norm(X - ref, axis=1)
+    den = np.linalg.norm(absref, axis=1)
+    out = np.where(den > 0, num / np.where(den > 0, den, 1.0), np.where(num == 0, 0.0, np.inf))
+    return out
+
+
+def abs_forward(a, B):
+    """|A| |B| by the oracle: the per-row error scale of C = A B."""
+    return oracle.spmm(a.m, a.k, a.row_ptr, a.col_idx, np.abs(a.vals), np.abs(B))
+
+
+def abs_transposed(a, G):
+    """|A|^T |G| by the oracle: the per-row error scale of dB = A^T G."""
+    return oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, np.abs(a.vals), np.abs(G))
+
+
+def abs_sddmm(a, G, B):
+    """<|G_row(e)|, |B_col(e)|> by the oracle: the error scale of each dA[e]."""
+    return oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, np.abs(G), np.abs(B))
+
+
+# Per-row bars of scaled_row_errors.  Rounding each input of a product to the
+# compute type moves it by at most 2u |a||b| (u = 2^-53 FP64, 2^-24 FP32,
+# 2^-11 FP16, 2^-8 BF16), and an FP32 (FP64) sum of L terms adds at most
+# L u_acc sum |a||b|; rows here have at most a few thousand terms.  The bars
+# sit a few times above those bounds.
+ROW_TOL = {torch.float64: 1e-12, torch.float32: 1e-5, torch.float16: 2e-3, torch.bfloat16: 1e-2}

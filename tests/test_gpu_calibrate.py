@@ -9,7 +9,7 @@ import torch
 import gen
 import oracle
 from oracle import loops_ref as L
-from tests.gpu_util import make_plan, oracle_forward, to_dev
+from tests.gpu_util import TOL, make_plan, oracle_forward, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -103,3 +103,10 @@ def test_calibrate_mixed_plan_other_dtypes(dtype):
     dB1, dA1 = plan.backward(B, G)
     torch.cuda.synchronize()
     assert torch.equal(dB0, dB1) and torch.equal(dA0, dA1)
+    # and against the FP64 oracle on the unrounded inputs
+    g = gen.dense(0, gen.GRAD, a.m, b.shape[1])
+    assert oracle.rel_err(C0, oracle_forward(a, b)) <= TOL[dtype]
+    assert oracle.rel_err(dB1.double().cpu().numpy(),
+                          oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, g)) <= TOL[dtype]
+    assert oracle.rel_err(dA1.double().cpu().numpy(),
+                          oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, g, b)) <= TOL[dtype]

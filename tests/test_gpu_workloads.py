@@ -1,8 +1,10 @@
 """Parity at the workloads' full sizes, in the launch configuration the
 benchmark times (AUTO split unless stated), against the FP64 oracle.
 
-Power law 2^20 x 2^20 (FP16/BF16 vs FP32), GCN graph 232,965 nodes (FP32
-forward + backward), and members of the structure sweep (FP64/FP32/FP16).
+Power law 2^20 x 2^20 (FP16/BF16 vs FP32; forward on sampled rows at both
+widths, the whole forward + backward step element by element at n = 64),
+GCN graph 232,965 nodes (FP32 forward + backward), and members of the
+structure sweep at their full row counts (FP64/FP32/FP16).
 """
 import numpy as np
 import pytest
@@ -10,7 +12,8 @@ import torch
 
 import gen
 import oracle
-from tests.gpu_util import TOL, effective_vals, make_plan, quantized_dense, to_dev
+from tests.gpu_util import (ROW_TOL, TOL, abs_forward, abs_sddmm, abs_transposed, effective_vals, make_plan,
+                            quantized_dense, scaled_row_errors, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -112,3 +115,32 @@ def test_sweep_members(i):
             C = plan.run(to_dev(b, dtype))
             torch.cuda.synchronize()
             assert oracle.rel_err(C.double().cpu().numpy(), ref) <= TOL[dtype], (dtype, split)
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16, torch.float32])
+def test_powerlaw_backward_full_size(powerlaw, dtype):
+    """The power-law workload's whole step at 2^20 rows, n = 64: C, dB =
+    A^T dC (through the transposed plan, whose hub columns become rows of up
+    to thousands of entries) and dA = SDDMM(dC, B), every element against the
+    FP64 oracle on the unrounded inputs, by Frobenius norm and row by row."""
+    a, b = powerlaw
+    n = 64
+    b = np.ascontiguousarray(b[:, :n])
+    G = gen.dense(0, gen.GRAD, a.m, n)
+    print(f"powerlaw backward dtype={dtype}", flush=True)
+    plan = make_plan(hs, a, dtype, "auto", backward=True, n_hint=n)
+    Bd = to_dev(b, dtype)
+    C = plan.run(Bd)
+    dB, dA = plan.backward(Bd, to_dev(G, torch.float32))
+    torch.cuda.synchronize()
+    C, dB, dA = (t.double().cpu().numpy() for t in (C, dB, dA))
+    checks = (
+        ("C", C, oracle.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, b), abs_forward(a, b)),
+        ("dB", dB, oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, G), abs_transposed(a, G)),
+        ("dA", dA, oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, G, b), abs_sddmm(a, G, b)),
+    )
+    for name, x, ref, absref in checks:
+        assert oracle.rel_err(x, ref) <= TOL[dtype], name
+        worst = float(scaled_row_errors(x, ref, absref).max())
+        print(f"  {name}: rel {oracle.rel_err(x, ref):.2e}, worst row {worst:.2e}", flush=True)
+        assert worst <= ROW_TOL[dtype], name
