@@ -104,6 +104,11 @@ typedef struct {
      * TP_csr = m / pred_us_csr_all and TP_bcsr = m / pred_us_bcsr_all with
      * t_csr = t_bcsr = 1) */
     double  pred_us_csr_all, pred_us_bcsr_all;
+    /* groups of BCSR row blocks sharing columns (FP32 / FP64 plans): the
+     * group kernels stage each group's shared columns in LDS once */
+    int64_t ngroups;              /* 0: the BCSR-part runs ungrouped */
+    int64_t grp_staged_tiles;     /* tiles that read their B row from the stage */
+    int64_t grp_stage_rows;       /* staged rows summed over the groups */
 } hspmm_plan_info;
 
 /* Build a plan for A (m x k, nnz entries, CSR) -- Alg. 1 plus the cost model.
@@ -194,7 +199,13 @@ typedef enum {
     HSPMM_F_BLK_PTR = 8,   /* int32 [rb_bcsr+1] */
     HSPMM_F_BLK_COL = 9,   /* int32 [nblk] */
     HSPMM_F_BLK_VAL = 10,  /* compute dtype [nblk][B_r] */
-    HSPMM_F_RB_SCALE = 11  /* FP64 [nrb]: power-of-two scale (1 for F32/F64) */
+    HSPMM_F_RB_SCALE = 11, /* FP64 [nrb]: power-of-two scale (1 for F32/F64) */
+    HSPMM_F_GRP_PTR = 12,  /* int32 [ngroups+1]: groups as ranges of GRP_RB */
+    HSPMM_F_GRP_RB = 13,   /* int32 [rb_bcsr]: row blocks in the group kernels' order */
+    HSPMM_F_GRP_UPTR = 14, /* int32 [ngroups+1]: groups as ranges of GRP_UCOL */
+    HSPMM_F_GRP_UCOL = 15, /* int32: each group's staged columns, ascending */
+    HSPMM_F_BLK_BSRC = 16  /* int32 [nblk], tiles as BLK_COL: stage row >= 0, or
+                              -(column + 1) for a tile gathered directly */
 } hspmm_field;
 
 int hybrid_spmm_export(hspmm_plan_t p, int32_t which, int32_t field, void* dst,

@@ -234,6 +234,7 @@ class Plan:
             dt = _NP_OF[ct]
         elif field == "rb_scale":
             dt = np.float64
+        # the group fields (int32) fall through to the default
         else:
             dt = np.int32
         buf = np.empty(nbytes.value // np.dtype(dt).itemsize, dtype=dt)

@@ -17,6 +17,7 @@ SPLIT = {"auto": 0, "csr": 1, "csr_only": 1, "bcsr": 2, "bcsr_only": 2, "boundar
 FIELDS = {
     "rb_class": 0, "rb_nnz": 1, "rb_nblk": 2, "csr_rows": 3, "csr_ptr": 4, "csr_col": 5,
     "csr_val": 6, "bcsr_rb": 7, "blk_ptr": 8, "blk_col": 9, "blk_val": 10, "rb_scale": 11,
+    "grp_ptr": 12, "grp_rb": 13, "grp_uptr": 14, "grp_ucol": 15, "blk_bsrc": 16,
 }
 
 STATUS = {
@@ -61,6 +62,7 @@ class PlanInfo(ctypes.Structure):
         ("has_backward", ctypes.c_int32),
         ("t_rows_csr", ctypes.c_int64), ("t_rb_bcsr", ctypes.c_int64), ("t_nblk", ctypes.c_int64),
         ("pred_us_csr_all", ctypes.c_double), ("pred_us_bcsr_all", ctypes.c_double),
+        ("ngroups", ctypes.c_int64), ("grp_staged_tiles", ctypes.c_int64), ("grp_stage_rows", ctypes.c_int64),
     ]
 
 

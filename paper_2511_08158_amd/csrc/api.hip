@@ -309,6 +309,9 @@ int hybrid_spmm_plan_info(hspmm_plan_t h, hspmm_plan_info* info) {
     i.t_nblk = p.T.nblk;
     i.pred_us_csr_all = p.A.pred_all_csr * 1e6;
     i.pred_us_bcsr_all = p.A.pred_all_bcsr * 1e6;
+    i.ngroups = p.A.grouped ? p.A.ngroups : 0;
+    i.grp_staged_tiles = p.A.grouped ? p.A.grp_staged : 0;
+    i.grp_stage_rows = p.A.grouped ? p.A.grp_union : 0;
     *info = i;
     return HSPMM_OK;
 }
@@ -375,6 +378,40 @@ int hybrid_spmm_export(hspmm_plan_t h, int32_t which, int32_t field, void* dst, 
                     }
                 }
             }
+            break;
+        }
+        case HSPMM_F_GRP_PTR:
+        case HSPMM_F_GRP_RB:
+        case HSPMM_F_GRP_UPTR:
+        case HSPMM_F_GRP_UCOL: {
+            std::vector<int32_t> v;
+            if (X.grouped) {
+                if (field == HSPMM_F_GRP_RB) {
+                    for (int32_t o : X.h_order) v.push_back(X.h_bcsr_rb[o]);
+                } else {
+                    const DevBuf& d = field == HSPMM_F_GRP_PTR ? X.grp_ptr
+                                      : field == HSPMM_F_GRP_UPTR ? X.grp_uptr : X.grp_ucol;
+                    size_t cnt = field == HSPMM_F_GRP_UCOL ? (size_t)X.grp_union : (size_t)X.ngroups + 1;
+                    v.resize(cnt);
+                    if (cnt) HIP_TRY(hipMemcpy(v.data(), d.ptr, cnt * 4, hipMemcpyDeviceToHost));
+                }
+            }
+            put_i32(v);
+            break;
+        }
+        case HSPMM_F_BLK_BSRC: {
+            std::vector<int32_t> v;
+            if (X.grouped) {
+                std::vector<uint8_t> raw;
+                HSPMM_TRY(fetch(X.blk_bsrc, (size_t)X.nblk_pad * 4, raw));
+                for (size_t sl = 0; sl < X.h_blk_cnt.size(); ++sl)
+                    for (int32_t b = 0; b < X.h_blk_cnt[sl]; ++b) {
+                        int32_t x;
+                        memcpy(&x, raw.data() + ((size_t)X.h_blk_ptr[sl] + b) * 4, 4);
+                        v.push_back(x);
+                    }
+            }
+            put_i32(v);
             break;
         }
         case HSPMM_F_RB_SCALE: {

@@ -216,4 +216,12 @@ int hybrid_launch_mode();
 
 constexpr int kNumXcd = 8;
 
+// LDS stage of the group kernels: rows of 256 bytes of the dense operand
+// (one column panel); the default and the largest number of staged rows a
+// group may hold
+constexpr int kGroupRowBytes = 256;
+constexpr int kGroupStageRows = 300;
+constexpr int kGroupMaxBlocks = 4;
+constexpr int kGroupStageRowsMax = 620;
+
 }  // namespace hspmm

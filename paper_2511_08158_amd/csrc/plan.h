@@ -50,6 +50,17 @@ struct SubPlan {
 
     DevBuf scale;                 // double [nrb] (scaled sub-plans only)
 
+    // groups of row blocks that share columns (group.h): the group kernels
+    // visit the BCSR row blocks in the order kslot_* (groups contiguous,
+    // group g = kernel slots [grp_ptr[g], grp_ptr[g + 1])), stage the columns
+    // grp_ucol[grp_uptr[g] ..] in LDS and read each tile's B row from the
+    // stage row blk_bsrc[tile] >= 0 or from column -(blk_bsrc + 1)
+    bool grouped = false;
+    int64_t ngroups = 0, grp_max_u = 0, grp_staged = 0, grp_union = 0;
+    DevBuf kslot_rb, kslot_ptr, kslot_cnt, kslot_chunk;
+    DevBuf grp_ptr, grp_uptr, grp_ucol, blk_bsrc;
+    std::vector<int32_t> h_order;  // kernel slot -> canonical slot (grouped only)
+
     // workgroup partition of the fused launch (0 = one workgroup per work
     // unit); set by calibration
     int32_t part_csr = 0, part_bcsr = 0;

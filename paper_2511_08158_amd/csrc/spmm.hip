@@ -374,6 +374,14 @@ __device__ void bcsr_wg_f(const BcsrArgs& a, const DenseArgs& d, const UnitMeta&
 // on the block stencil FP32 n = 128: forward 34.9 -> 33.5 us, FP64 68.2 ->
 // 65.6 us against the four-wave split with its LDS reduction.
 constexpr int kWaveMaxTiles = 2048;
+// load batches in flight in the one-wave FP32 / FP64 walk: 2; 3 (loads of
+// batch b + 2 issued before the MFMAs of batch b) measured the same for FP32
+// and slower for FP64 on the block stencil (forward 39.3 vs 38.6 us, FP64
+// 64.0 vs 58.9 us)
+#ifndef HSPMM_WAVE_DEPTH
+#define HSPMM_WAVE_DEPTH 2
+#endif
+constexpr int kWaveDepth = HSPMM_WAVE_DEPTH;
 template <class T, int VEC, int NL, int SB>
 __device__ inline void load_wave_steps(const T* __restrict__ vals, const T* __restrict__ B, int64_t ldb, int64_t n,
                                        int b0, int q, int lane, int colreg, int s0, int slast, int st,
@@ -391,7 +399,7 @@ __device__ inline void load_wave_steps(const T* __restrict__ vals, const T* __re
     }
 }
 
-template <class T, int VEC, int NL>
+template <class T, int VEC, int NL, int DEPTH = 2>
 __device__ void bcsr_wave_f(const BcsrArgs& a, const DenseArgs& d, int64_t unit) {
     typedef typename AccOf<T>::type acc_v;
     constexpr int PANEL = 16 * VEC * NL;
@@ -419,6 +427,31 @@ __device__ void bcsr_wave_f(const BcsrArgs& a, const DenseArgs& d, int64_t unit)
         constexpr int SB = sizeof(T) == 8 ? 2 : 1;
         StepRegs<T, VEC, NL, SB> x, y;
         load_wave_steps<T, VEC, NL, SB>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1, s0, cbase, x);
+        if constexpr (DEPTH == 3) {
+            // three batches in flight: the loads of batch b + 2 are issued
+            // before the MFMAs of batch b
+            StepRegs<T, VEC, NL, SB> z;
+            load_wave_steps<T, VEC, NL, SB>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1, s0 + SB, cbase,
+                                            y);
+            for (int sr = s0; sr < send; sr += 3 * SB) {
+                load_wave_steps<T, VEC, NL, SB>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1, sr + 2 * SB,
+                                                cbase, z);
+                __builtin_amdgcn_sched_barrier(0);
+                mfma_steps<T, acc_v, VEC, NL, SB>(x, acc, sr, send);
+                __builtin_amdgcn_sched_barrier(0);
+                load_wave_steps<T, VEC, NL, SB>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1, sr + 3 * SB,
+                                                cbase, x);
+                __builtin_amdgcn_sched_barrier(0);
+                mfma_steps<T, acc_v, VEC, NL, SB>(y, acc, sr + SB, send);
+                __builtin_amdgcn_sched_barrier(0);
+                load_wave_steps<T, VEC, NL, SB>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1, sr + 4 * SB,
+                                                cbase, y);
+                __builtin_amdgcn_sched_barrier(0);
+                mfma_steps<T, acc_v, VEC, NL, SB>(z, acc, sr + 2 * SB, send);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            continue;
+        }
         for (int sr = s0; sr < send; sr += 2 * SB) {
             load_wave_steps<T, VEC, NL, SB>(vals, B, d.ldb, d.n, b0, q, lane, colreg, s0, send - 1, sr + SB, cbase,
                                             y);
@@ -446,6 +479,179 @@ __device__ void bcsr_wave_f(const BcsrArgs& a, const DenseArgs& d, int64_t unit)
             for (int v = 0; v < VEC; ++v) o[v] = acc[h * VEC + v][r] * sc;
             store_vec<T, VEC>(static_cast<T*>(d.C) + row * d.ldc + col, o);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BCSR-part in groups of row blocks that share columns, FP32 / FP64
+// ---------------------------------------------------------------------------
+// One workgroup per (group, column panel of 256 bytes).  It copies the
+// panel of every column the group's tiles use into LDS with direct
+// global -> LDS loads (all of a wave's copies in flight at once), and while
+// they are in flight each wave loads the values and stage rows of its first
+// row block; its four waves then take the group's row blocks in turn and
+// run the MFMA walk of bcsr_wave_f over them with every B operand read from
+// LDS.  A column several row blocks of the group use is fetched once per
+// group instead of once per tile, and the walk waits on no global load.
+struct GroupArgs {
+    const int32_t* rb;        // kernel slot -> row block
+    const int32_t* blk_ptr;   // kernel slot -> first stored tile
+    const int32_t* blk_cnt;   // kernel slot -> real tiles
+    const int32_t* grp_ptr;   // [ngroups + 1]: kernel slots of each group
+    const int32_t* grp_uptr;  // [ngroups + 1]: staged columns of each group
+    const int32_t* ucol;
+    const int32_t* bsrc;      // per stored tile: its row of the group's stage
+    const void* val;
+    int64_t ngroups;
+    int32_t n_panels;
+};
+
+// operands of up to 32 MFMA steps (128 tiles) of one row block: the values
+// of row (lane & 15) of tile (lane >> 4) of each step, and the stage row of
+// tile 64 h + lane in bs[h]
+template <class T>
+struct GBlock {
+    T av[32];
+    int bs[2];
+};
+
+template <class T>
+__device__ inline void load_gblock(const T* __restrict__ vals, const int32_t* __restrict__ bsrc, int b0, int nsteps,
+                                   int st0, int lane, GBlock<T>& o) {
+    const int last = nsteps - 1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int tt = 4 * st0 + 64 * h + lane;
+        o.bs[h] = tt < 4 * nsteps ? bsrc[b0 + tt] : 0;
+    }
+#pragma unroll
+    for (int t = 0; t < 32; ++t) o.av[t] = vals[(int64_t)(b0 + 4 * min(st0 + t, last)) * 16 + lane];
+}
+
+template <class T, int VEC>
+__device__ void bcsr_group_f(const GroupArgs& a, const DenseArgs& d, int64_t unit, T* lds, int* lidx) {
+    typedef typename AccOf<T>::type acc_v;
+    constexpr int PANEL = 16 * VEC;                     // 256 bytes of a B row
+    constexpr int RS = kGroupRowBytes / (int)sizeof(T);  // LDS row stride, elements
+    constexpr int CH = 16 / (int)sizeof(T);             // elements per 16-byte copy
+    static_assert(PANEL * (int)sizeof(T) == kGroupRowBytes, "a panel is one staged row");
+    const int64_t grp = unit / a.n_panels;
+    if (grp >= a.ngroups) return;  // uniform over the workgroup
+    const int panel = (int)(unit - grp * a.n_panels);
+    const int64_t pcol0 = (int64_t)panel * PANEL;
+    const int s0 = a.grp_ptr[grp], s1 = a.grp_ptr[grp + 1];
+    const int u0 = a.grp_uptr[grp], U = a.grp_uptr[grp + 1] - u0;
+    const T* __restrict__ B = static_cast<const T*>(d.B);
+    const T* __restrict__ vals = static_cast<const T*>(a.val);
+    const int lane = threadIdx.x & 63, w = wave_id(), j = lane & 15, q = lane >> 4;
+
+    // the stage's columns into LDS, and this wave's first row block, before
+    // any copy is issued (the copies and the block's operand loads below
+    // then wait on no global load for their addresses)
+    int sl = s0 + w;
+    int rb = 0, b0 = 0, nsteps = 0;
+    if (sl < s1) {
+        rb = a.rb[sl];
+        b0 = a.blk_ptr[sl];
+        nsteps = (a.blk_cnt[sl] + 3) >> 2;
+    }
+    for (int i = threadIdx.x; i < U; i += 256) lidx[i] = a.ucol[u0 + i];
+    __syncthreads();
+    // the stage: four rows per wave instruction (lane l copies 16 bytes of
+    // row r0 + l / 16); columns past n copy column 0 (their results are
+    // never stored); a wave's last copy may fill up to three rows past U
+    // with the stage's first column
+    {
+        const int64_t col = pcol0 + (lane & 15) * CH;
+        const int64_t gc = col < d.n ? col : 0;
+        for (int r0 = 4 * w; r0 < U; r0 += 16) {
+            const int r = r0 + (lane >> 4);
+            const int64_t brow = lidx[r < U ? r : 0];
+            __builtin_amdgcn_global_load_lds(B + brow * d.ldb + gc, lds + r0 * RS, 16, 0, 0);
+        }
+    }
+    // the operands of this wave's first row block, loaded while the stage
+    // is in flight
+    GBlock<T> blk;
+    if (sl < s1) load_gblock<T>(vals, a.bsrc, b0, nsteps, 0, lane, blk);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    const int64_t cb = pcol0 + (int64_t)j * VEC;
+    const bool colok = cb < d.n;
+    const T* lrow = lds + j * VEC;
+    for (; sl < s1; sl += 4) {
+        acc_v acc[VEC];
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) acc[t] = acc_v{0, 0, 0, 0};
+        for (int st0 = 0; st0 < nsteps; st0 += 32) {
+            if (st0 > 0) load_gblock<T>(vals, a.bsrc, b0, nsteps, st0, lane, blk);
+            // four steps at a time, the B operands of the next four read
+            // from LDS while the MFMAs of these run; a step past the row
+            // block's last multiplies zero values (its stage row is row 0)
+            T bc[4][VEC];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int bs = __shfl(blk.bs[0], (4 * k + q) & 63, 64);
+                load_vec<T, VEC>(lrow + bs * RS, bc[k]);
+            }
+#pragma unroll
+            for (int t4 = 0; t4 < 32; t4 += 4) {
+                if (st0 + t4 >= nsteps) break;  // uniform over the wave
+                T bn[4][VEC];
+                if (t4 + 4 < 32) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int t = t4 + 4 + k;
+                        const int bs = __shfl(blk.bs[t >> 4], (4 * (t & 15) + q) & 63, 64);
+                        load_vec<T, VEC>(lrow + bs * RS, bn[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const T x = st0 + t4 + k < nsteps ? blk.av[t4 + k] : T(0);
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) acc[v] = mfma4(x, bc[k][v], acc[v]);
+                }
+                if (t4 + 4 < 32) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v) bc[k][v] = bn[k][v];
+                }
+            }
+        }
+        const T sc = d.scale ? (T)d.scale[rb] : T(1);
+        if (colok) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = (int64_t)rb * 16 + out_row<T>(q, r);
+                if (row >= d.m) continue;
+                T o[VEC];
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) o[v] = acc[v][r] * sc;
+                store_vec<T, VEC>(static_cast<T*>(d.C) + row * d.ldc + cb, o);
+            }
+        }
+        if (sl + 4 < s1) {
+            rb = a.rb[sl + 4];
+            b0 = a.blk_ptr[sl + 4];
+            nsteps = (a.blk_cnt[sl + 4] + 3) >> 2;
+            load_gblock<T>(vals, a.bsrc, b0, nsteps, 0, lane, blk);
+        }
+    }
+}
+
+template <class T, int VEC>
+__global__ __launch_bounds__(256) void k_bcsr_group(GroupArgs ga, DenseArgs da, uint32_t g, int remap,
+                                                    int stage_rows) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* stage = reinterpret_cast<T*>(lds_raw);
+    int* lidx = reinterpret_cast<int*>(lds_raw + (size_t)(stage_rows + 4) * kGroupRowBytes);
+    const int64_t units = ga.ngroups * (int64_t)ga.n_panels;
+    for (int64_t unit = (int64_t)xcd_remap(blockIdx.x, g, remap); unit < units; unit += g) {
+        bcsr_group_f<T, VEC>(ga, da, unit, stage, lidx);
+        __syncthreads();  // the stage is rewritten by the next unit
     }
 }
 
@@ -670,7 +876,7 @@ void k_hybrid(CsrArgs ca, BcsrArgs ba, DenseArgs da, uint32_t g_bcsr, uint32_t g
             } else if constexpr (WAVE) {
                 // four units per workgroup, one per wave
                 for (int64_t u4 = (int64_t)xcd_remap(bid, g_bcsr, remap); u4 * 4 < units; u4 += g_bcsr)
-                    bcsr_wave_f<TV, BV, BNL>(ba, da, u4 * 4 + w);
+                    bcsr_wave_f<TV, BV, BNL, kWaveDepth>(ba, da, u4 * 4 + w);
             } else {
                 // a contiguous range of units per workgroup (neighbouring row
                 // blocks share gathered rows of B in the XCD's L2)
@@ -790,14 +996,25 @@ void launch_long_reduce(const SubPlan& X, const DenseArgs& d, hipStream_t s) {
 
 inline uint32_t pad8(int64_t g) { return (uint32_t)(ceil_div(g, 8) * 8); }
 
+// 1 (default): grouped BCSR-parts run the LDS-staged group kernel; 0
+// (HSPMM_GROUP_KERNEL=0): the one-wave kernel in group order
+int group_kernel_mode() {
+    const char* e = getenv("HSPMM_GROUP_KERNEL");
+    return (e && e[0] == '0') ? 0 : 1;
+}
+
 template <class TV, class TB, class TC, int VEC, int LPR, int BV, int BNL, bool WAVE>
 int launch_cfg_w(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuery* q) {
     CsrArgs ca{X.vr_start.as<int32_t>(), X.vr_end.as<int32_t>(), X.vr_out.as<int32_t>(),
                X.csr_col.as<int32_t>(), X.csr_val.ptr, X.n_vrows};
     constexpr int PANEL = (sizeof(TV) == 2) ? 16 * BV : 16 * BV * BNL;
     const int32_t n_panels = (int32_t)ceil_div(d.n, PANEL);
-    BcsrArgs ba{X.bcsr_rb.as<int32_t>(), X.blk_ptr.as<int32_t>(), X.blk_cnt.as<int32_t>(),
-                X.blk_col.as<int32_t>(), X.blk_val.ptr, X.rb_bcsr, n_panels};
+    // a grouped plan's row blocks in group order: the four waves of a
+    // workgroup take neighbouring row blocks of one group
+    const bool gord = X.grouped;
+    BcsrArgs ba{(gord ? X.kslot_rb : X.bcsr_rb).as<int32_t>(), (gord ? X.kslot_ptr : X.blk_ptr).as<int32_t>(),
+                (gord ? X.kslot_cnt : X.blk_cnt).as<int32_t>(), X.blk_col.as<int32_t>(), X.blk_val.ptr, X.rb_bcsr,
+                n_panels};
     constexpr int R = 64 / LPR;
     const int64_t csr_waves = ceil_div(X.n_vrows, R);
     const int64_t bcsr_units = X.rb_bcsr * (int64_t)n_panels;
@@ -881,6 +1098,57 @@ int launch_cfg_w(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuer
     return HSPMM_OK;
 }
 
+// A grouped BCSR-part (FP32 / FP64 with 16-byte rows of B and C): the
+// group kernel for it, the CSR-part (if any) as its own launch, then the
+// reduction of split CSR rows.
+template <class TV, class TB, class TC, int VEC, int LPR, int BV, int BNL>
+int launch_grouped(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuery* q) {
+    constexpr int PANEL = 16 * BV;
+    const int32_t n_panels = (int32_t)ceil_div(d.n, PANEL);
+    GroupArgs ga{X.kslot_rb.as<int32_t>(), X.kslot_ptr.as<int32_t>(), X.kslot_cnt.as<int32_t>(),
+                 X.grp_ptr.as<int32_t>(), X.grp_uptr.as<int32_t>(), X.grp_ucol.as<int32_t>(),
+                 X.blk_bsrc.as<int32_t>(), X.blk_val.ptr, X.ngroups, n_panels};
+    CsrArgs ca{X.vr_start.as<int32_t>(), X.vr_end.as<int32_t>(), X.vr_out.as<int32_t>(),
+               X.csr_col.as<int32_t>(), X.csr_val.ptr, X.n_vrows};
+    BcsrArgs ba{};
+    constexpr int R = 64 / LPR;
+    const int64_t csr_waves = ceil_div(X.n_vrows, R);
+    uint32_t g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
+    const int64_t units = X.ngroups * (int64_t)n_panels;
+    uint32_t g_grp = units ? pad8(units) : 0;
+    // the stage, the up to three rows a wave's last copy may run past it,
+    // and the stage's column indices
+    const size_t lds = (size_t)(X.grp_max_u + 4) * kGroupRowBytes + (size_t)std::max<int64_t>(1, X.grp_max_u) * 4;
+    if (X.part_csr > 0 && g_csr > (uint32_t)X.part_csr) g_csr = pad8(X.part_csr);
+    if (X.part_bcsr > 0 && g_grp > (uint32_t)X.part_bcsr) g_grp = pad8(X.part_bcsr);
+    if (q) {
+        q->g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
+        q->g_bcsr = units ? pad8(units) : 0;
+        int nb = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void*>(&k_bcsr_group<TV, BV>), 256, lds));
+        q->wg_per_cu = nb;
+        return HSPMM_OK;
+    }
+    const int rm = xcd_remap_mode();
+    if (g_grp) {
+        hipLaunchKernelGGL((k_bcsr_group<TV, BV>), dim3(g_grp), dim3(256), lds, s, ga, d, g_grp, rm,
+                           (int)X.grp_max_u);
+        HIP_LAUNCH_CHECK();
+    }
+    if (g_csr) {
+        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, false, false>), dim3(g_csr), dim3(256), 0,
+                           s, ca, ba, d, 0u, g_csr, rm);
+        HIP_LAUNCH_CHECK();
+    }
+    if (X.n_long > 0) {
+        typedef typename Elem<TB>::acc_t acc_t;
+        launch_long_reduce<TC, acc_t>(X, d, s);
+        HIP_LAUNCH_CHECK();
+    }
+    return HSPMM_OK;
+}
+
 // BCSR-parts whose row blocks are all short run one wave per row block
 // The FP16 / BF16 one-wave form holds 3-4 waves per SIMD; a fused launch
 // with a large CSR-part is held there too, which costs the CSR-part more
@@ -889,6 +1157,10 @@ int launch_cfg_w(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuer
 // quarter of the entries (BCSR-only forward 26.5 -> 21.5 us).
 template <class TV, class TB, class TC, int VEC, int LPR, int BV, int BNL>
 int launch_cfg(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuery* q) {
+    if constexpr (sizeof(TV) != 2 && BV * sizeof(TV) == 16) {
+        if (X.grouped && X.rb_bcsr > 0 && group_kernel_mode())
+            return launch_grouped<TV, TB, TC, VEC, LPR, BV, BNL>(X, d, s, q);
+    }
     const bool wave_ok = sizeof(TV) != 2 || 3 * X.nnz_csr <= X.nnz_bcsr;
     if (X.rb_bcsr > 0 && X.max_rb_tiles <= kWaveMaxTiles && wave_ok)
         return launch_cfg_w<TV, TB, TC, VEC, LPR, BV, BNL, true>(X, d, s, q);
