@@ -243,6 +243,15 @@ typedef struct {
 int hybrid_spmm_calibrate(hspmm_plan_t p, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc,
                           int32_t reps, hspmm_calib_info* info, void* stream);
 
+/* Kernel timing for callers that measure the products (benchmarks,
+ * profilers): while set, every product this thread launches (run, the dB
+ * and dA halves of backward, run_noalloc) records `start` (a hipEvent_t) as
+ * its first kernel begins and `stop` as its last kernel ends, from the
+ * kernels' own dispatch timestamps, so no marker separates the kernels of
+ * consecutive calls.  NULL, NULL clears them.  The events must have been
+ * created with timing enabled; this thread only.  Errors: none. */
+int hybrid_spmm_set_timing_events(void* start, void* stop);
+
 /* Release the plan and all its device memory (NULL-safe). */
 void hybrid_spmm_destroy(hspmm_plan_t p);
 

@@ -21,7 +21,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["Plan", "spmm", "HspmmError", "DTYPES", "library"]
+__all__ = ["Plan", "spmm", "HspmmError", "DTYPES", "library", "set_timing_events", "check_dense"]
 
 DTYPES = {torch.float64: _lib.F64, torch.float32: _lib.F32, torch.float16: _lib.F16,
           torch.bfloat16: _lib.BF16}
@@ -45,6 +45,22 @@ def _check(rc: int):
     if rc != 0:
         msg = library().hybrid_spmm_last_error().decode(errors="replace")
         raise HspmmError(rc, msg)
+
+
+def set_timing_events(start=None, stop=None):
+    """Make every product this thread launches record the torch.cuda.Event
+    `start` as its first kernel begins and `stop` as its last kernel ends
+    (the kernels' own timestamps); no arguments clear them.  The events are
+    recorded once on the current stream first so that they exist."""
+    handles = []
+    for e in (start, stop):
+        if e is None:
+            handles.append(None)
+            continue
+        if not e.cuda_event:
+            e.record()
+        handles.append(ctypes.c_void_p(e.cuda_event))
+    _check(library().hybrid_spmm_set_timing_events(*handles))
 
 
 def _ptr(t):

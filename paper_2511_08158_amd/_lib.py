@@ -90,6 +90,7 @@ EXPORTED = [
     "hybrid_spmm_plan", "hybrid_spmm_run", "hybrid_spmm_backward", "hybrid_spmm_update_values",
     "hybrid_spmm_plan_info", "hybrid_spmm_export", "hybrid_spmm_destroy",
     "hybrid_spmm_last_error", "hybrid_spmm_version", "hybrid_spmm_calibrate", "hybrid_spmm_run_noalloc",
+    "hybrid_spmm_set_timing_events",
 ]
 
 _lib = None
@@ -113,6 +114,8 @@ def load():
     L.hybrid_spmm_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.hybrid_spmm_export.argtypes = [vp, i32, i32, vp, i64, ctypes.POINTER(i64)]
     L.hybrid_spmm_calibrate.argtypes = [vp, i64, vp, i64, vp, i64, i32, ctypes.POINTER(CalibInfo), vp]
+    L.hybrid_spmm_set_timing_events.argtypes = [vp, vp]
+    L.hybrid_spmm_set_timing_events.restype = ctypes.c_int
     L.hybrid_spmm_destroy.argtypes = [vp]
     L.hybrid_spmm_destroy.restype = None
     for f in (L.hybrid_spmm_plan, L.hybrid_spmm_run, L.hybrid_spmm_run_noalloc, L.hybrid_spmm_backward,

@@ -10,7 +10,10 @@ namespace hspmm {
 
 namespace {
 thread_local std::string g_last_error;
+thread_local KernelTiming g_timing;
 }
+
+const KernelTiming& kernel_timing() { return g_timing; }
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 const char* last_error_cstr() { return g_last_error.c_str(); }
@@ -452,6 +455,13 @@ void hybrid_spmm_destroy(hspmm_plan_t h) {
 
 const char* hybrid_spmm_last_error(void) { return hspmm::last_error_cstr(); }
 
-const char* hybrid_spmm_version(void) { return "hspmm 0.1.0 (gfx950)"; }
+int hybrid_spmm_set_timing_events(void* start, void* stop) {
+    clear_error();
+    g_timing.start = static_cast<hipEvent_t>(start);
+    g_timing.stop = static_cast<hipEvent_t>(stop);
+    return HSPMM_OK;
+}
+
+const char* hybrid_spmm_version(void) { return "hspmm 0.2.0 (gfx950)"; }
 
 }  // extern "C"

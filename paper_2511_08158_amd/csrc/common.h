@@ -1,6 +1,7 @@
 // Shared definitions of the hspmm HIP library (gfx950 only).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -215,6 +216,25 @@ int bwd_concurrent();
 int hybrid_launch_mode();
 
 constexpr int kNumXcd = 8;
+
+// Events the caller asked the next products to carry (hybrid_spmm_set_
+// timing_events; this thread only): the first kernel a product launches
+// records `start` as it begins and the last records `stop` as it ends, from
+// the kernels' own dispatch timestamps (no marker between the kernels).
+struct KernelTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+const KernelTiming& kernel_timing();
+
+#define HSPMM_LAUNCH(KERNEL, GRID, BLOCK, LDS, STREAM, FIRST, LAST, ...)                                  \
+    do {                                                                                                \
+        const ::hspmm::KernelTiming& _kt = ::hspmm::kernel_timing();                                    \
+        if (_kt.start || _kt.stop)                                                                      \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, STREAM, (FIRST) ? _kt.start : nullptr,     \
+                                  (LAST) ? _kt.stop : nullptr, 0, __VA_ARGS__);                         \
+        else                                                                                            \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, STREAM, __VA_ARGS__);                          \
+    } while (0)
 
 // LDS stage of the group kernels: rows of 256 bytes of the dense operand
 // (one column panel); the default and the largest number of staged rows a

@@ -468,7 +468,7 @@ inline int lpr_for(int64_t n, int vec) {
 }
 
 template <class TB, class TG, int VEC, int LPR, int BVEC, int NKR>
-int launch_sdd(const SubPlan& X, SddArgs a, hipStream_t s) {
+int launch_sdd(const SubPlan& X, SddArgs a, hipStream_t s, bool last) {
     constexpr int R = 64 / LPR;
     const int64_t csr_waves = ceil_div(X.n_vrows, R);
     const uint32_t g_csr = csr_waves ? pad8(ceil_div(csr_waves, 4)) : 0;
@@ -480,20 +480,20 @@ int launch_sdd(const SubPlan& X, SddArgs a, hipStream_t s) {
     const dim3 grid(g_bcsr + g_csr), block(256);
     const int rm = xcd_remap_mode();
     if (g_bcsr && g_csr && hybrid_launch_mode() == 2) {
-        hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, false, true>), dim3(g_bcsr), block, lds, s, a, g_bcsr,
-                           0u, rm);
+        HSPMM_LAUNCH((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, false, true>), dim3(g_bcsr), block, lds, s, true, false, a,
+                     g_bcsr, 0u, rm);
         HIP_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, true, false>), dim3(g_csr), block, 0, s, a, 0u, g_csr,
-                           rm);
+        HSPMM_LAUNCH((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, true, false>), dim3(g_csr), block, 0, s, false, last, a, 0u,
+                     g_csr, rm);
     } else if (g_bcsr && g_csr) {
-        hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, true, true>), grid, block, lds, s, a, g_bcsr, g_csr,
-                           rm);
+        HSPMM_LAUNCH((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, true, true>), grid, block, lds, s, true, last, a, g_bcsr,
+                     g_csr, rm);
     } else if (g_csr) {
-        hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, true, false>), grid, block, 0, s, a, g_bcsr, g_csr,
-                           rm);
+        HSPMM_LAUNCH((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, true, false>), grid, block, 0, s, true, last, a, g_bcsr,
+                     g_csr, rm);
     } else {
-        hipLaunchKernelGGL((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, false, true>), grid, block, lds, s, a, g_bcsr,
-                           g_csr, rm);
+        HSPMM_LAUNCH((k_sddmm<TB, TG, VEC, LPR, BVEC, NKR, false, true>), grid, block, lds, s, true, last, a, g_bcsr,
+                     g_csr, rm);
     }
     HIP_LAUNCH_CHECK();
     return HSPMM_OK;
@@ -540,46 +540,47 @@ int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC,
                   X.blk_cnt.as<int32_t>(), X.blk_col.as<int32_t>(), X.chunk_ptr.as<int32_t>(),
                   X.chunk_base.as<int32_t>(), static_cast<const uint16_t*>(X.chunk_mask.ptr), X.rb_bcsr, B, ldb, dC, lddc, n, X.m, target};
         const size_t eb = dtype_size(X.ct);
+        const bool last = p.canonical;  // else the gather to input order follows
         const int rc = [&]() -> int {
             switch (X.ct) {
                 case HSPMM_F32: {
                     const bool v = n % 4 == 0 && ldb % 4 == 0 && lddc % 4 == 0 && aligned(B, 16) && aligned(dC, 16);
-                    if (!v) return launch_sdd<float, float, 1, 64, 1, 32>(X, a, s);
-                    HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<float, float, 4, LPR, 4, 8>(X, a, s)));
+                    if (!v) return launch_sdd<float, float, 1, 64, 1, 32>(X, a, s, last);
+                    HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<float, float, 4, LPR, 4, 8>(X, a, s, last)));
                 }
                 case HSPMM_F64: {
                     const bool v = n % 2 == 0 && ldb % 2 == 0 && lddc % 2 == 0 && aligned(B, 16) && aligned(dC, 16);
-                    if (!v) return launch_sdd<double, double, 1, 64, 1, 32>(X, a, s);
-                    HSPMM_LPR_SWITCH(lpr_for(n, 2), return (launch_sdd<double, double, 2, LPR, 2, 16>(X, a, s)));
+                    if (!v) return launch_sdd<double, double, 1, 64, 1, 32>(X, a, s, last);
+                    HSPMM_LPR_SWITCH(lpr_for(n, 2), return (launch_sdd<double, double, 2, LPR, 2, 16>(X, a, s, last)));
                 }
                 case HSPMM_F16: {
                     const bool v = n % 4 == 0 && ldb % 4 == 0 && lddc % 4 == 0 && aligned(B, 8) && aligned(dC, 16);
-                    if (!v) return launch_sdd<half_t, float, 1, 64, 1, 32>(X, a, s);
+                    if (!v) return launch_sdd<half_t, float, 1, 64, 1, 32>(X, a, s, last);
                     // the FP16 MFMA form: n a multiple of 8 up to 256, 16-byte rows of B
                     if (n % 8 == 0 && n <= 256 && ldb % 8 == 0 && aligned(B, 16)) {
                         if (n <= 128)
                             HSPMM_LPR_SWITCH(lpr_for(n, HSPMM_SDD_H_VEC),
-                                             return (launch_sdd<half_t, float, HSPMM_SDD_H_VEC, LPR, 8, 4>(X, a, s)));
+                                             return (launch_sdd<half_t, float, HSPMM_SDD_H_VEC, LPR, 8, 4>(X, a, s, last)));
                         HSPMM_LPR_SWITCH(lpr_for(n, HSPMM_SDD_H_VEC),
-                                         return (launch_sdd<half_t, float, HSPMM_SDD_H_VEC, LPR, 8, 8>(X, a, s)));
+                                         return (launch_sdd<half_t, float, HSPMM_SDD_H_VEC, LPR, 8, 8>(X, a, s, last)));
                     }
-                    HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<half_t, float, 4, LPR, 4, 8>(X, a, s)));
+                    HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<half_t, float, 4, LPR, 4, 8>(X, a, s, last)));
                 }
                 case HSPMM_BF16: {
                     const bool v = n % 4 == 0 && ldb % 4 == 0 && lddc % 4 == 0 && aligned(B, 8) && aligned(dC, 16);
-                    if (!v) return launch_sdd<bf16_t, float, 1, 64, 1, 32>(X, a, s);
+                    if (!v) return launch_sdd<bf16_t, float, 1, 64, 1, 32>(X, a, s, last);
                     // the BF16 MFMA form: n a multiple of 8 up to 256, 16-byte rows of B
                     if (n % 8 == 0 && n <= 256 && ldb % 8 == 0 && aligned(B, 16)) {
                         if (n <= 128)
                             HSPMM_LPR_SWITCH(lpr_for(n, HSPMM_SDD_H_VEC),
-                                             return (launch_sdd<bf16_t, float, HSPMM_SDD_H_VEC, LPR, 8, 4>(X, a, s)));
+                                             return (launch_sdd<bf16_t, float, HSPMM_SDD_H_VEC, LPR, 8, 4>(X, a, s, last)));
                         HSPMM_LPR_SWITCH(lpr_for(n, HSPMM_SDD_H_VEC),
-                                         return (launch_sdd<bf16_t, float, HSPMM_SDD_H_VEC, LPR, 8, 8>(X, a, s)));
+                                         return (launch_sdd<bf16_t, float, HSPMM_SDD_H_VEC, LPR, 8, 8>(X, a, s, last)));
                     }
                     if (n % 8 == 0 && ldb % 8 == 0 && aligned(B, 16))
                         HSPMM_LPR_SWITCH(lpr_for(n, HSPMM_SDD_H_VEC),
-                                         return (launch_sdd<bf16_t, float, HSPMM_SDD_H_VEC, LPR, 4, 8>(X, a, s)));
-                    HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<bf16_t, float, 4, LPR, 4, 8>(X, a, s)));
+                                         return (launch_sdd<bf16_t, float, HSPMM_SDD_H_VEC, LPR, 4, 8>(X, a, s, last)));
+                    HSPMM_LPR_SWITCH(lpr_for(n, 4), return (launch_sdd<bf16_t, float, 4, LPR, 4, 8>(X, a, s, last)));
                 }
                 default: return fail(HSPMM_ERR_DTYPE, "bad compute dtype");
             }
@@ -591,11 +592,11 @@ int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC,
     if (!p.canonical) {
         const unsigned g = (unsigned)std::min<int64_t>(ceil_div(p.nnz_in, 256), 65536);
         if (go == 8) {
-            hipLaunchKernelGGL(k_gather_dA<double>, dim3(g), dim3(256), 0, s, ws.as<double>(),
-                               p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<double*>(dA));
+            HSPMM_LAUNCH(k_gather_dA<double>, dim3(g), dim3(256), 0, s, false, true, ws.as<double>(),
+                         p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<double*>(dA));
         } else {
-            hipLaunchKernelGGL(k_gather_dA<float>, dim3(g), dim3(256), 0, s, ws.as<float>(),
-                               p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<float*>(dA));
+            HSPMM_LAUNCH(k_gather_dA<float>, dim3(g), dim3(256), 0, s, false, true, ws.as<float>(),
+                         p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<float*>(dA));
         }
         HIP_LAUNCH_CHECK();
     }

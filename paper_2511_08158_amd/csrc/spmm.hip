@@ -984,8 +984,8 @@ void launch_long_reduce(const SubPlan& X, const DenseArgs& d, hipStream_t s) {
     const Acc* ws = static_cast<const Acc*>(d.ws);
     TC* C = static_cast<TC*>(d.C);
 #define HSPMM_LR(VV, BB)                                                                                     \
-    hipLaunchKernelGGL((k_long_reduce<TC, Acc, VV, BB>), grid, dim3(BB), 0, s, X.long_row.as<int32_t>(),   \
-                       X.long_first.as<int32_t>(), X.long_cnt.as<int32_t>(), ws, C, d.ldc, d.n, L, d.scale)
+    HSPMM_LAUNCH((k_long_reduce<TC, Acc, VV, BB>), grid, dim3(BB), 0, s, false, true, X.long_row.as<int32_t>(), \
+                 X.long_first.as<int32_t>(), X.long_cnt.as<int32_t>(), ws, C, d.ldc, d.n, L, d.scale)
     if (vec) {
         if (big) HSPMM_LR(VW, 1024); else HSPMM_LR(VW, 256);
     } else {
@@ -1072,22 +1072,23 @@ int launch_cfg_w(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQuer
     }
     const dim3 grid(g_bcsr + g_csr), block(256);
     const int rm = xcd_remap_mode();
+    const bool last = X.n_long == 0;  // no reduction kernel follows
     if (g_bcsr && g_csr && hybrid_launch_mode() == 2) {
         // the two parts as two kernels, each with its own register budget
-        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, false, true, WAVE>), dim3(g_bcsr), block, lds, s,
-                           ca, ba, d, g_bcsr, 0u, rm);
+        HSPMM_LAUNCH((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, false, true, WAVE>), dim3(g_bcsr), block, lds, s, true,
+                     false, ca, ba, d, g_bcsr, 0u, rm);
         HIP_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, false, false>), dim3(g_csr), block, 0, s, ca,
-                           ba, d, 0u, g_csr, rm);
+        HSPMM_LAUNCH((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, false, false>), dim3(g_csr), block, 0, s, false,
+                     last, ca, ba, d, 0u, g_csr, rm);
     } else if (g_bcsr && g_csr) {
-        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, true, WAVE>), grid, block, lds, s, ca, ba, d,
-                           g_bcsr, g_csr, rm);
+        HSPMM_LAUNCH((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, true, WAVE>), grid, block, lds, s, true, last, ca,
+                     ba, d, g_bcsr, g_csr, rm);
     } else if (g_csr) {
-        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, false, false>), grid, block, 0, s, ca, ba, d,
-                           g_bcsr, g_csr, rm);
+        HSPMM_LAUNCH((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, false, false>), grid, block, 0, s, true, last, ca,
+                     ba, d, g_bcsr, g_csr, rm);
     } else {
-        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, false, true, WAVE>), grid, block, lds, s, ca, ba, d,
-                           g_bcsr, g_csr, rm);
+        HSPMM_LAUNCH((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, false, true, WAVE>), grid, block, lds, s, true, last, ca,
+                     ba, d, g_bcsr, g_csr, rm);
     }
     HIP_LAUNCH_CHECK();
     if (X.n_long > 0) {
@@ -1132,13 +1133,13 @@ int launch_grouped(const SubPlan& X, const DenseArgs& d, hipStream_t s, LaunchQu
     }
     const int rm = xcd_remap_mode();
     if (g_grp) {
-        hipLaunchKernelGGL((k_bcsr_group<TV, BV>), dim3(g_grp), dim3(256), lds, s, ga, d, g_grp, rm,
-                           (int)X.grp_max_u);
+        HSPMM_LAUNCH((k_bcsr_group<TV, BV>), dim3(g_grp), dim3(256), lds, s, true, !g_csr && !X.n_long, ga, d, g_grp,
+                     rm, (int)X.grp_max_u);
         HIP_LAUNCH_CHECK();
     }
     if (g_csr) {
-        hipLaunchKernelGGL((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, false, false>), dim3(g_csr), dim3(256), 0,
-                           s, ca, ba, d, 0u, g_csr, rm);
+        HSPMM_LAUNCH((k_hybrid<TV, TB, TC, VEC, LPR, BV, BNL, true, false, false>), dim3(g_csr), dim3(256), 0, s,
+                     !g_grp, !X.n_long, ca, ba, d, 0u, g_csr, rm);
         HIP_LAUNCH_CHECK();
     }
     if (X.n_long > 0) {

@@ -190,3 +190,38 @@ def test_binding_rejects_bad_operands():
     torch.cuda.synchronize()
     ref = oracle.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, np.ones((a.k, 8)))
     assert oracle.rel_err(C.double().cpu().numpy(), ref) <= 1e-5
+
+
+def test_timing_events_bracket_the_kernels():
+    """hybrid_spmm_set_timing_events: the products record the given events
+    from their kernels' own timestamps -- positive durations that add up to
+    no more than the step bracketed by ordinary events -- the results are
+    unchanged, and clearing the events leaves later products untimed."""
+    a, b = gen.config2(grid=32)
+    g = gen.dense(0, gen.GRAD, a.m, b.shape[1])
+    plan = make_plan(hs, a, torch.float32, "auto", backward=True)
+    B = to_dev(b, torch.float32)
+    dC = to_dev(g, torch.float32)
+    ref = plan.run(B)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    for e in ev:
+        e.record()
+    torch.cuda.synchronize()
+    ev[6].record()
+    hs.set_timing_events(ev[0], ev[1])
+    C = plan.run(B)
+    hs.set_timing_events(ev[2], ev[3])
+    dB, _ = plan.backward(B, dC, need_dA=False)
+    hs.set_timing_events(ev[4], ev[5])
+    _, dA = plan.backward(B, dC, need_dB=False)
+    hs.set_timing_events()
+    ev[7].record()
+    C2 = plan.run(B)
+    torch.cuda.synchronize()
+    ks = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(3)]
+    assert all(t > 0 for t in ks), ks
+    assert sum(ks) <= ev[6].elapsed_time(ev[7]) + 1e-3
+    assert torch.equal(C, ref) and torch.equal(C2, ref)
+    assert oracle.rel_err(dB.double().cpu().numpy(),
+                          oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, g)) <= 1e-5
+    assert oracle.rel_err(dA.double().cpu().numpy(), oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, g, b)) <= 1e-5
