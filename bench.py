@@ -68,8 +68,10 @@ def parse():
                     help="only run a plain 1 GiB device copy 10 times (calibrates HBM byte counters)")
     ap.add_argument("--sweep", action="store_true",
                     help="structure sweep: forward GFLOP/s of the AUTO split vs CSR-only per matrix and N")
-    ap.add_argument("--sweep-rows", type=int, default=100_000, help="row cap of the sweep matrices")
+    ap.add_argument("--sweep-rows", type=int, default=500_000, help="row cap of the sweep matrices")
     ap.add_argument("--sweep-n", default="16,32,64,128,256")
+    ap.add_argument("--sweep-dtypes", default="f64,f32,f16", help="compute precisions of the sweep")
+    ap.add_argument("--sweep-members", default="0-63", help="sweep members, e.g. 0-31 or 3,7")
     ap.add_argument("--gcn-train", action="store_true",
                     help="time a two-layer graph-convolution training loop on the 232,965-node graph")
     ap.add_argument("--epochs", type=int, default=20)
@@ -104,11 +106,28 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def _members(spec):
+    out = []
+    for part in spec.split(","):
+        if "-" in part:
+            lo, hi = part.split("-")
+            out.extend(range(int(lo), int(hi) + 1))
+        elif part:
+            out.append(int(part))
+    return out
+
+
 def sweep(args):
-    """Forward throughput of AUTO vs CSR-only over the 64 seeded matrices of
-    the structure sweep (uniform / banded / block-diagonal / power law),
-    FP32, one JSON line per (matrix, N) and a summary line.  The BCSR-only
-    plan is timed too, so AUTO is also compared with the better fixed split."""
+    """Forward throughput of AUTO vs CSR-only (and BCSR-only) over the 64
+    seeded matrices of the structure sweep (uniform / banded / block-diagonal
+    / power law, rows log-uniform in 1k-500k), in each compute precision and
+    at each width: one JSON line per (matrix, precision, n) and a summary
+    line per precision.  Each plan is timed warm, as the fastest of 6 batches
+    of launches (about 2 ms of the CSR-only plan per batch, at most 20
+    launches), the three plans' batches interleaved in rotating order (small
+    matrices run 7-12 us per launch, where single batches of one plan spread
+    by 10 % and more).  Sampled rows of every AUTO result are checked
+    against their definition computed row by row in FP64."""
     import numpy as np
     import torch
 
@@ -117,83 +136,93 @@ def sweep(args):
 
     dev = torch.device("cuda:0")
     ns = [int(x) for x in args.sweep_n.split(",")]
-    wins, ratios, rows, best_ratios = 0, [], [], []
-    for i in range(64):
+    tdt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+    dts = [d for d in args.sweep_dtypes.split(",") if d]
+    tol = {"f64": 1e-12, "f32": 1e-5, "f16": 5e-3, "bf16": 5e-3}
+    rows = []
+    splits = ("auto", "csr", "bcsr")
+    for i in _members(args.sweep_members):
         a = gen.config5(i, max_rows=args.sweep_rows)
         spec = a.meta
         vals = torch.tensor(a.vals, device=dev)
-        for n in ns:
-            b = gen.dense(i, gen.DENSE, a.k, n, "uniform")
-            B = torch.tensor(b, device=dev, dtype=torch.float32)
-            res = {}
-            splits = ("auto", "csr", "bcsr")
-            plans = {sp_: hs.Plan(a.row_ptr, a.col_idx, vals, (a.m, a.k), compute=torch.float32, split=sp_,
-                                  n_hint=n) for sp_ in splits}
-            outs = {}
-            for sp_, p in plans.items():
-                outs[sp_] = p.run(B)
-                for _ in range(3):
-                    p.run(B, out=outs[sp_])
-            # the fastest of 9 batches of 20 launches per plan, the plans'
-            # batches interleaved: small matrices run for 7-12 us per launch,
-            # where single batches of one plan spread by 10 % and more
-            reps, best = 20, {sp_: float("inf") for sp_ in splits}
-            for rnd in range(9):
-                # the order rotates so that every plan is timed first as often
-                for sp_ in splits[rnd % 3:] + splits[:rnd % 3]:
-                    p = plans[sp_]
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record()
-                    for _ in range(reps):
+        g = np.random.default_rng(i)
+        rs = np.sort(g.choice(a.m, min(a.m, 256), replace=False))
+        for dname in dts:
+            dt = tdt[dname]
+            od = torch.float64 if dt == torch.float64 else torch.float32
+            # the fixed splits do not depend on n; AUTO is planned per n
+            fixed = {sp_: hs.Plan(a.row_ptr, a.col_idx, vals, (a.m, a.k), compute=dt, split=sp_)
+                     for sp_ in ("csr", "bcsr")}
+            for n in ns:
+                b = gen.dense(i, gen.DENSE, a.k, n, "uniform")
+                B = torch.tensor(b, device=dev).to(dt)
+                plans = {"auto": hs.Plan(a.row_ptr, a.col_idx, vals, (a.m, a.k), compute=dt, split="auto",
+                                         n_hint=n), **fixed}
+                outs = {}
+                for sp_, p in plans.items():
+                    outs[sp_] = torch.empty((a.m, n), dtype=od, device=dev)
+                    for _ in range(2):
                         p.run(B, out=outs[sp_])
-                    e1.record()
-                    torch.cuda.synchronize()
-                    best[sp_] = min(best[sp_], e0.elapsed_time(e1) / reps * 1e-3)
-            for sp_, p in plans.items():
-                t = best[sp_]
-                info = p.info()
-                res[sp_] = {"t": t, "gflops": 2.0 * a.nnz * n / t / 1e9, "rb_bcsr": info["rb_bcsr"],
-                            "rows_csr": info["rows_csr"], "fill": info["fill"]}
-                if sp_ == "auto" and n == ns[0]:
-                    # sampled rows against their definition, row by row in FP64
-                    g = np.random.default_rng(i)
-                    rs = np.sort(g.choice(a.m, min(a.m, 256), replace=False))
-                    ref = np.stack([a.vals[a.row_ptr[r]:a.row_ptr[r + 1]] @ b[a.col_idx[a.row_ptr[r]:a.row_ptr[r + 1]]]
-                                    for r in rs])
-                    res["err"] = rel_err(outs[sp_][torch.as_tensor(rs, device=dev)].double().cpu().numpy(), ref)
+                # launches per batch: about 2 ms of the CSR-only plan, at most 20
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                plans["csr"].run(B, out=outs["csr"])
+                e1.record()
+                torch.cuda.synchronize()
+                reps = int(min(20, max(1, round(2.0 / max(e0.elapsed_time(e1), 1e-3)))))
+                best = {sp_: float("inf") for sp_ in splits}
+                for rnd in range(6):
+                    for sp_ in splits[rnd % 3:] + splits[:rnd % 3]:
+                        p = plans[sp_]
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record()
+                        for _ in range(reps):
+                            p.run(B, out=outs[sp_])
+                        e1.record()
+                        torch.cuda.synchronize()
+                        best[sp_] = min(best[sp_], e0.elapsed_time(e1) / reps * 1e-3)
+                info = plans["auto"].info()
+                line = {"i": i, "class": spec["class"], "m": a.m, "nnz": a.nnz, "dtype": dname, "n": n,
+                        "auto_gflops": round(2.0 * a.nnz * n / best["auto"] / 1e9, 1),
+                        "csr_gflops": round(2.0 * a.nnz * n / best["csr"] / 1e9, 1),
+                        "bcsr_gflops": round(2.0 * a.nnz * n / best["bcsr"] / 1e9, 1),
+                        "speedup": round(best["csr"] / best["auto"], 3),
+                        "vs_best_fixed": round(min(best["csr"], best["bcsr"]) / best["auto"], 3),
+                        "rb_bcsr": info["rb_bcsr"], "rb_total": (a.m + 15) // 16, "fill": round(info["fill"], 3)}
+                # sampled rows of the AUTO result against their definition,
+                # row by row in FP64 on the unrounded operands
+                ref = np.stack([a.vals[a.row_ptr[r]:a.row_ptr[r + 1]] @ b[a.col_idx[a.row_ptr[r]:a.row_ptr[r + 1]]]
+                                for r in rs])
+                got = outs["auto"][torch.as_tensor(rs, device=dev)].double().cpu().numpy()
+                line["err"] = float(f"{rel_err(got, ref):.2e}")
+                line["err_ok"] = line["err"] <= tol[dname]
+                plans["auto"].close()
+                del outs, B
+                rows.append(line)
+                print(json.dumps(line), flush=True)
+            for p in fixed.values():
                 p.close()
-            sp = res["csr"]["t"] / res["auto"]["t"]
-            ratios.append(sp)
-            best_ratios.append(min(res["csr"]["t"], res["bcsr"]["t"]) / res["auto"]["t"])
-            wins += sp >= 0.98
-            line = {"i": i, "class": spec["class"], "m": a.m, "nnz": a.nnz, "n": n,
-                    "auto_gflops": round(res["auto"]["gflops"], 1), "csr_gflops": round(res["csr"]["gflops"], 1),
-                    "bcsr_gflops": round(res["bcsr"]["gflops"], 1), "speedup": round(sp, 3), "rb_bcsr": res["auto"]["rb_bcsr"],
-                    "rb_total": (a.m + 15) // 16, "fill": round(res["auto"]["fill"], 3)}
-            if "err" in res:
-                line["err"] = float(f"{res['err']:.2e}")
-            rows.append(line)
-            print(json.dumps(line), flush=True)
-    gm = float(np.exp(np.mean(np.log(ratios))))
-    # runs whose AUTO plan is the CSR-only plan (no BCSR row block): the
-    # same launches, so their measured ratio shows the timing spread alone
-    same = np.array([r["rb_bcsr"] == 0 for r in rows])
-    rat = np.array(ratios)
-    eq = np.where(same, 1.0, rat)
-    best_eq = np.where(same, np.array([r["csr_gflops"] / max(r["csr_gflops"], r["bcsr_gflops"]) for r in rows]),
-                       np.array(best_ratios))
-    print(json.dumps({"sweep_summary": {"runs": len(ratios), "auto_not_slower_share": round(wins / len(ratios), 3),
-                                        "geomean_speedup_auto_vs_csr": round(gm, 3),
-                                        "max_speedup": round(max(ratios), 3), "min_speedup": round(min(ratios), 3),
-                                        "geomean_auto_vs_best_fixed": round(float(np.exp(np.mean(np.log(best_ratios)))), 3),
-                                        "min_auto_vs_best_fixed": round(min(best_ratios), 3),
-                                        "runs_auto_is_csr_only_plan": int(same.sum()),
-                                        "timing_spread_same_plan": [round(float(rat[same].min()), 3),
-                                                                    round(float(rat[same].max()), 3)] if same.any() else None,
-                                        "auto_not_slower_share_same_plan_equal": round(float(np.mean(eq >= 0.98)), 3),
-                                        "geomean_auto_vs_csr_same_plan_equal": round(float(np.exp(np.mean(np.log(eq)))), 3),
-                                        "geomean_auto_vs_best_fixed_same_plan_equal": round(float(np.exp(np.mean(np.log(best_eq)))), 3),
-                                        "max_err": max(r.get("err", 0.0) for r in rows)}}), flush=True)
+    for dname in dts:
+        rr = [r for r in rows if r["dtype"] == dname]
+        if not rr:
+            continue
+        rat = np.array([r["speedup"] for r in rr])
+        same = np.array([r["rb_bcsr"] == 0 for r in rr])
+        eq = np.where(same, 1.0, rat)
+        best_eq = np.where(same, np.array([r["csr_gflops"] / max(r["csr_gflops"], r["bcsr_gflops"]) for r in rr]),
+                           np.array([r["vs_best_fixed"] for r in rr]))
+        print(json.dumps({"sweep_summary": {
+            "dtype": dname, "runs": len(rr),
+            "auto_not_slower_share": round(float(np.mean(rat >= 0.98)), 3),
+            "auto_not_slower_share_same_plan_equal": round(float(np.mean(eq >= 0.98)), 3),
+            "geomean_speedup_auto_vs_csr": round(float(np.exp(np.mean(np.log(rat)))), 3),
+            "geomean_speedup_auto_vs_csr_same_plan_equal": round(float(np.exp(np.mean(np.log(eq)))), 3),
+            "geomean_auto_vs_best_fixed_same_plan_equal": round(float(np.exp(np.mean(np.log(best_eq)))), 3),
+            "max_speedup": round(float(rat.max()), 3), "min_speedup": round(float(rat.min()), 3),
+            "runs_auto_is_csr_only_plan": int(same.sum()),
+            "timing_spread_same_plan": [round(float(rat[same].min()), 3), round(float(rat[same].max()), 3)]
+            if same.any() else None,
+            "max_err": max(r["err"] for r in rr), "all_err_ok": all(r["err_ok"] for r in rr)}}), flush=True)
 
 
 def gcn_train(args):

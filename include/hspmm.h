@@ -59,7 +59,13 @@ typedef enum { HSPMM_F64 = 0, HSPMM_F32 = 1, HSPMM_F16 = 2, HSPMM_BF16 = 3 } hsp
  *   BCSR_ONLY every row block in the BCSR-part (r_boundary = 0, the pure
  *             matrix-unit mode of Sec. 4.3);
  *   BOUNDARY  contiguous split of Alg. 1: rows [0, r_boundary) CSR, the rest
- *             BCSR; r_boundary < 0 solves Eq. 1 (balanced predicted times). */
+ *             BCSR; r_boundary = -1 solves Eq. 1 with the cost model's
+ *             predicted times, HSPMM_R_MEASURED solves it with throughputs
+ *             measured on this matrix at plan time (the warm-up runs of
+ *             Sec. 3.1: the forward of the whole matrix is timed once in
+ *             the CSR-part and once in the BCSR-part at width n_hint, and
+ *             TP = m / time). */
+#define HSPMM_R_MEASURED (-2)
 typedef enum {
     HSPMM_SPLIT_AUTO = 0,
     HSPMM_SPLIT_CSR_ONLY = 1,
@@ -72,7 +78,8 @@ typedef struct {
     int32_t compute;              /* hspmm_dtype of the A-parts and of B */
     int32_t split;                /* hspmm_split */
     int32_t block_rows;           /* B_r: 16 (0 = 16); the MFMA tile height */
-    int64_t r_boundary;           /* BOUNDARY only; < 0 = solve Eq. 1 */
+    int64_t r_boundary;           /* BOUNDARY only; -1 = solve Eq. 1 (model),
+                                     HSPMM_R_MEASURED = solve it (measured) */
     int32_t n_hint;               /* expected n for the cost model (0 = 128) */
     int32_t want_backward;        /* nonzero: also build the transposed plan */
     uint64_t max_workspace_bytes; /* 0 = unlimited; larger plans fail with OOM */
@@ -109,6 +116,9 @@ typedef struct {
     int64_t ngroups;              /* 0: the BCSR-part runs ungrouped */
     int64_t grp_staged_tiles;     /* tiles that read their B row from the stage */
     int64_t grp_stage_rows;       /* staged rows summed over the groups */
+    /* HSPMM_R_MEASURED plans: the measured forward time of the whole matrix
+     * in each part at n_hint, the inputs of the measured Eq. 1 (0 otherwise) */
+    double  meas_us_csr_all, meas_us_bcsr_all;
 } hspmm_plan_info;
 
 /* Build a plan for A (m x k, nnz entries, CSR) -- Alg. 1 plus the cost model.

@@ -13,6 +13,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libhspmm.so"
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
 SPLIT = {"auto": 0, "csr": 1, "csr_only": 1, "bcsr": 2, "bcsr_only": 2, "boundary": 3, "eq1": 3}
+R_MEASURED = -2  # BOUNDARY with Eq. 1 solved on throughputs measured at plan time
 
 FIELDS = {
     "rb_class": 0, "rb_nnz": 1, "rb_nblk": 2, "csr_rows": 3, "csr_ptr": 4, "csr_col": 5,
@@ -63,6 +64,7 @@ class PlanInfo(ctypes.Structure):
         ("t_rows_csr", ctypes.c_int64), ("t_rb_bcsr", ctypes.c_int64), ("t_nblk", ctypes.c_int64),
         ("pred_us_csr_all", ctypes.c_double), ("pred_us_bcsr_all", ctypes.c_double),
         ("ngroups", ctypes.c_int64), ("grp_staged_tiles", ctypes.c_int64), ("grp_stage_rows", ctypes.c_int64),
+        ("meas_us_csr_all", ctypes.c_double), ("meas_us_bcsr_all", ctypes.c_double),
     ]
 
 

@@ -315,6 +315,8 @@ int hybrid_spmm_plan_info(hspmm_plan_t h, hspmm_plan_info* info) {
     i.ngroups = p.A.grouped ? p.A.ngroups : 0;
     i.grp_staged_tiles = p.A.grouped ? p.A.grp_staged : 0;
     i.grp_stage_rows = p.A.grouped ? p.A.grp_union : 0;
+    i.meas_us_csr_all = p.meas_csr * 1e6;
+    i.meas_us_bcsr_all = p.meas_bcsr * 1e6;
     *info = i;
     return HSPMM_OK;
 }

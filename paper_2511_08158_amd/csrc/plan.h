@@ -87,6 +87,8 @@ struct Plan {
     SubPlan A, T;
     bool has_T = false;
 
+    double meas_csr = 0.0, meas_bcsr = 0.0;  // measured whole-matrix forward time of each part (s)
+
     DevBuf ws;            // run/backward scratch
     DevBuf ws2;           // scratch of the SDDMM when it runs beside dB
     // scratch buffers replaced by larger ones: work already queued may still

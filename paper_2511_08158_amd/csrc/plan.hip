@@ -491,7 +491,7 @@ int build_sub_groups(Plan& p, SubPlan& X, hipStream_t s) {
 // Build one sub-plan from a canonical CSR (device rp[m+1], col, row_of) whose
 // entry x stands for A's canonical entry src[x] (src null = identity).
 int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const int32_t* row_of,
-              const int32_t* src, hipStream_t s) {
+              const int32_t* src, hipStream_t s, int split_override = -1, int64_t r_override = -1) {
     Allocator& al = p.al;
     const int64_t m = X.m, n = X.nnz;
     const int br = X.br;
@@ -504,7 +504,7 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
     X.h_rb_nnz.assign(nrb, 0);
     for (int64_t q = 0; q < nrb; ++q) X.h_rb_nnz[q] = h_rp[std::min<int64_t>(m, q * br + br)] - h_rp[q * br];
 
-    const int split = p.opts.split;
+    const int split = split_override >= 0 ? split_override : p.opts.split;
     const bool need_tiles = split != HSPMM_SPLIT_CSR_ONLY && n > 0;
     DevBuf ord, hd, hx, total;
     X.h_rb_nblk.assign(nrb, 0);
@@ -538,7 +538,7 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
     } else if (split == HSPMM_SPLIT_BCSR_ONLY) {
         X.h_cls.assign(nrb, 1);
     } else if (split == HSPMM_SPLIT_BOUNDARY) {
-        int64_t rbd = p.opts.r_boundary;
+        int64_t rbd = r_override >= 0 ? r_override : p.opts.r_boundary;
         if (&X == &p.T || rbd < 0) {
             // Eq. 1: the aggregate throughput of each part is m / (its
             // predicted time for the whole matrix)
@@ -786,9 +786,8 @@ int pack_sub_any(Plan& p, SubPlan& X, const double* vb, int act, hipStream_t s) 
 
 }  // namespace
 
-int pack_values(Plan& p, const void* vals, int vals_dtype, hipStream_t s) {
-    if (p.nnz == 0) return HSPMM_OK;
-    DevBuf vb;
+// vb[c]: the canonical values of A in FP64 (duplicates summed in input order)
+int canonical_values(Plan& p, const void* vals, int vals_dtype, DevBuf& vb, hipStream_t s) {
     HSPMM_TRY(p.al.alloc(vb, (size_t)p.nnz * 8));
     const int32_t* perm = p.canonical ? nullptr : p.perm.as<int32_t>();
     const int32_t* seg = p.canonical ? nullptr : p.seg.as<int32_t>();
@@ -801,15 +800,73 @@ int pack_values(Plan& p, const void* vals, int vals_dtype, hipStream_t s) {
         default: return fail(HSPMM_ERR_DTYPE, "bad vals dtype");
     }
     HIP_LAUNCH_CHECK();
-    if (p.A.scaled) {
-        hipLaunchKernelGGL(k_rb_scale, dim3(grid_waves(p.A.nrb)), dim3(kThreads), 0, s,
-                           p.canon_rp.as<int32_t>(), vb.as<double>(), p.m, p.A.nrb, p.A.scale.as<double>());
+    return HSPMM_OK;
+}
+
+// the power-of-two scales (scaled sub-plans) and the packed values of one
+// of A's sub-plans
+int pack_a_like(Plan& p, SubPlan& X, const double* vb, hipStream_t s) {
+    if (X.scaled) {
+        hipLaunchKernelGGL(k_rb_scale, dim3(grid_waves(X.nrb)), dim3(kThreads), 0, s, p.canon_rp.as<int32_t>(), vb,
+                           p.m, X.nrb, X.scale.as<double>());
         HIP_LAUNCH_CHECK();
     }
-    HSPMM_TRY(pack_sub_any(p, p.A, vb.as<double>(), -1, s));
+    return pack_sub_any(p, X, vb, -1, s);
+}
+
+int pack_values(Plan& p, const void* vals, int vals_dtype, hipStream_t s) {
+    if (p.nnz == 0) return HSPMM_OK;
+    DevBuf vb;
+    HSPMM_TRY(canonical_values(p, vals, vals_dtype, vb, s));
+    HSPMM_TRY(pack_a_like(p, p.A, vb.as<double>(), s));
     if (p.has_T) HSPMM_TRY(pack_sub_any(p, p.T, vb.as<double>(), p.compute, s));
     HIP_TRY(hipStreamSynchronize(s));
     p.al.free(vb);
+    return HSPMM_OK;
+}
+
+// Seconds per forward product of the whole matrix in one part (CSR_ONLY or
+// BCSR_ONLY) at width n_hint: a temporary sub-plan of A in that split,
+// packed, run twice to warm up and timed over five launches on a zero B.
+int time_whole_part(Plan& p, const SubPlan& like, int split, const int32_t* rp, const int32_t* col,
+                    const double* vb, hipStream_t s, double* secs) {
+    SubPlan X;
+    X.ct = like.ct;
+    X.m = like.m;
+    X.k = like.k;
+    X.nnz = like.nnz;
+    X.br = like.br;
+    X.kc = like.kc;
+    X.scaled = like.scaled;
+    HSPMM_TRY(build_sub(p, X, rp, col, p.row_of.as<int32_t>(), nullptr, s, split));
+    if (X.scaled) HSPMM_TRY(p.al.alloc(X.scale, std::max<int64_t>(1, X.nrb) * 8));
+    HSPMM_TRY(pack_a_like(p, X, vb, s));
+    const int64_t n = std::max<int32_t>(1, p.opts.n_hint);
+    const size_t eb = dtype_size(X.ct), ec = dtype_size(out_dtype(X.ct));
+    DevBuf B, C;
+    HSPMM_TRY(p.al.alloc(B, (size_t)std::max<int64_t>(1, X.k) * n * eb));
+    HSPMM_TRY(p.al.alloc(C, (size_t)std::max<int64_t>(1, X.m) * n * ec));
+    HSPMM_TRY(fill_i32(B.as<int32_t>(), 0, (int64_t)(B.bytes / 4), s));
+    for (int i = 0; i < 2; ++i) HSPMM_TRY(launch_forward(p, X, n, B.ptr, n, C.ptr, n, s));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    constexpr int reps = 5;
+    int rc = HSPMM_OK;
+    (void)hipEventRecord(e0, s);
+    for (int i = 0; i < reps && rc == HSPMM_OK; ++i) rc = launch_forward(p, X, n, B.ptr, n, C.ptr, n, s);
+    (void)hipEventRecord(e1, s);
+    float ms = 0.f;
+    if (rc == HSPMM_OK) {
+        hipError_t e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) rc = hip_fail(e, "timing a part", __FILE__, __LINE__);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HSPMM_TRY(rc);
+    HIP_TRY(hipStreamSynchronize(s));
+    *secs = (double)ms * 1e-3 / reps;
     return HSPMM_OK;
 }
 
@@ -917,7 +974,21 @@ int build_plan(Plan& p, const int32_t* row_ptr, const int32_t* col_idx, const vo
     A.br = p.br;
     A.kc = (p.compute == HSPMM_F16 || p.compute == HSPMM_BF16) ? 32 : 4;
     A.scaled = (p.compute == HSPMM_F16 || p.compute == HSPMM_BF16);
-    HSPMM_TRY(build_sub(p, A, crp.as<int32_t>(), ccol.as<int32_t>(), p.row_of.as<int32_t>(), nullptr, s));
+    int64_t r_meas = -1;
+    if (p.opts.split == HSPMM_SPLIT_BOUNDARY && p.opts.r_boundary == HSPMM_R_MEASURED && p.nnz > 0) {
+        // Eq. 1 with throughputs measured on this matrix (the paper's
+        // warm-up runs): TP of a part = m / (time of the whole matrix in it)
+        DevBuf vb;
+        HSPMM_TRY(canonical_values(p, vals, vals_dtype, vb, s));
+        HSPMM_TRY(time_whole_part(p, A, HSPMM_SPLIT_CSR_ONLY, crp.as<int32_t>(), ccol.as<int32_t>(), vb.as<double>(),
+                                  s, &p.meas_csr));
+        HSPMM_TRY(time_whole_part(p, A, HSPMM_SPLIT_BCSR_ONLY, crp.as<int32_t>(), ccol.as<int32_t>(),
+                                  vb.as<double>(), s, &p.meas_bcsr));
+        r_meas = eq1_boundary(m, p.meas_csr > 0 ? (double)m / p.meas_csr : 1.0, 1.0,
+                              p.meas_bcsr > 0 ? (double)m / p.meas_bcsr : 1.0, 1.0, p.br);
+    }
+    HSPMM_TRY(build_sub(p, A, crp.as<int32_t>(), ccol.as<int32_t>(), p.row_of.as<int32_t>(), nullptr, s, -1,
+                        r_meas));
     if (A.scaled) HSPMM_TRY(al.alloc(A.scale, std::max<int64_t>(1, A.nrb) * 8));
 
     // ---- transposed sub-plan for dB = A^T dC ----

@@ -225,3 +225,28 @@ def test_timing_events_bracket_the_kernels():
     assert oracle.rel_err(dB.double().cpu().numpy(),
                           oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, g)) <= 1e-5
     assert oracle.rel_err(dA.double().cpu().numpy(), oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, g, b)) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+def test_eq1_boundary_from_measured_throughputs(dtype):
+    """BOUNDARY with r_boundary = HSPMM_R_MEASURED: the plan times the
+    forward of the whole matrix in the CSR-part and in the BCSR-part and
+    solves Eq. 1 with TP = m / time; the boundary equals the oracle's Eq. 1
+    on the times the plan reports, the row blocks follow it, and the product
+    is the oracle's."""
+    from paper_2511_08158_amd import _lib
+    a, b = gen.config2(grid=32)
+    plan = make_plan(hs, a, dtype, "boundary", backward=True, r_boundary=_lib.R_MEASURED, n_hint=64)
+    info = plan.info()
+    tc, tb = info["meas_us_csr_all"], info["meas_us_bcsr_all"]
+    print(f"measured whole-matrix forward: CSR-part {tc:.1f} us, BCSR-part {tb:.1f} us, "
+          f"r_boundary {info['r_boundary']} of {a.m}", flush=True)
+    assert tc > 0 and tb > 0
+    want = L.eq1_boundary(a.m, a.m / tc, 1.0, a.m / tb, 1.0, 16)
+    assert info["r_boundary"] == want
+    cls = plan.export("rb_class").astype(bool)
+    assert np.array_equal(cls, np.arange(cls.size) * 16 >= want)
+    C = plan.run(to_dev(b, dtype))
+    torch.cuda.synchronize()
+    assert oracle.rel_err(C.double().cpu().numpy(),
+                          oracle.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, b)) <= TOL[dtype]
