@@ -11,10 +11,11 @@ RowBlockCost rowblock_cost(const MachineModel& mm, int64_t nnz, int64_t nblk, in
                            int br, int kc) {
     (void)sv;
     (void)br;
+    const PartRates& r = mm.rates(sb);
     RowBlockCost c;
-    c.t_csr = (double)nnz * (mm.t_entry + (double)n * sb / mm.bw_csr);
+    c.t_csr = (double)nnz * (r.t_entry + (double)n * sb / r.bw_csr);
     const int64_t padded = nblk == 0 ? 0 : ((nblk + kc - 1) / kc) * kc;
-    c.t_bcsr = (double)padded * std::max(mm.t_blk, (double)n * sb / mm.bw_bcsr);
+    c.t_bcsr = (double)padded * std::max(r.t_blk, (double)n * sb / r.bw_bcsr);
     return c;
 }
 

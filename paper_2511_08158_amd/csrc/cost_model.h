@@ -7,24 +7,30 @@
 
 namespace hspmm {
 
-// Machine constants of one MI355X used by the time model.  The rates are
-// effective figures of this library's two kernels, fitted to the forward
-// times of the CSR-only and BCSR-only plans of the 64-matrix structure sweep
-// (FP32, n = 16..256, relative least squares):
+// Machine constants of one MI355X used by the time model, one set per
+// precision of the dense operand (its element size s_b).  The rates are
+// effective figures of this library's two kernels, fitted by relative least
+// squares (with a per-launch constant that every plan pays alike) to the
+// forward times of the CSR-only and BCSR-only plans of the 64-matrix
+// structure sweep at its full sizes, n = 16..256, in that precision:
 //   CSR-part  = nnz * (t_entry + n s_b / bw_csr)       (one gathered B row
 //               segment per entry, through L2/MALL);
 //   BCSR-part = padded tiles * max(t_blk, n s_b / bw_bcsr)   (a tile costs
 //               its MFMA step, value and index loads until its gathered
-//               B row segment takes longer).
+//               B row segment takes longer; FP16/BF16 row blocks are padded
+//               to 32 tiles, FP32/FP64 to 4).
+struct PartRates {
+    double bw_csr, t_entry, bw_bcsr, t_blk;
+};
 struct MachineModel {
-    double bw_csr = 20.0e12;
-    double bw_bcsr = 6.5e12;
-    double t_entry = 0.0;
-    double t_blk = 31.0e-12;
+    PartRates f64{16.0e12, 0.0, 6.5e12, 34.6e-12};
+    PartRates f32{18.7e12, 1.0e-12, 6.5e12, 32.2e-12};
+    PartRates f16{13.4e12, 1.9e-12, 6.5e12, 17.3e-12};  // FP16 and BF16
     // extra time of a plan with both parts over a one-part plan (measured:
     // one ragged CSR row block beside a BCSR-part added 4.5 us)
     double t_mixed = 4.0e-6;
     int cus = 256;
+    const PartRates& rates(int sb) const { return sb >= 8 ? f64 : (sb == 4 ? f32 : f16); }
 };
 
 struct RowBlockCost {
