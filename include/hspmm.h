@@ -176,11 +176,28 @@ int hybrid_spmm_run_noalloc(hspmm_plan_t p, int64_t n, const void* B, int64_t ld
  * dA accumulates in FP32; for F16/BF16 plans the BCSR-part's rows (n a
  * multiple of 8, at most 256) first round each 16-row slab of dC to the
  * compute type after an exact power-of-two scale (largest magnitude in
- * [2^14, 2^15)), one rounding per dC element.  Errors: ARG, NO_BACKWARD (dB requested without
- * want_backward), HIP, OOM. */
+ * [2^14, 2^15)), one rounding per dC element.
+ * When both gradients are requested, an F32/F64 plan whose transposed plan
+ * is all BCSR-part computes them in one pass over the tiles of A^T: each
+ * tile's gathered row of dC serves its dB product and its entries' dA dot
+ * products (Sec. 3.3 product and its gradient; one gather stream instead of
+ * two), for n up to 256 (FP32) / 128 (FP64) with n, ldb, lddc, lddb
+ * multiples of 16 bytes and 16-byte aligned B, dC, dB.
+ * dB is then bitwise the separate product's; dA differs only in summation
+ * order.  Errors: ARG, NO_BACKWARD (dB requested without want_backward),
+ * HIP, OOM. */
 int hybrid_spmm_backward(hspmm_plan_t p, int64_t n, const void* B, int64_t ldb,
                          const void* dC, int64_t lddc, void* dB, int64_t lddb,
                          void* dA_vals, void* stream);
+
+/* Whether hybrid_spmm_backward with these operands and both outputs takes
+ * the one-pass path described above (*fused = 1) or runs dB and dA as
+ * separate products (*fused = 0).  dB may be NULL to ask about a 16-byte
+ * aligned dB (as a fresh allocation is) with the given lddb.  No device
+ * work.  Errors: ARG. */
+int hybrid_spmm_backward_fused(hspmm_plan_t p, int64_t n, const void* B, int64_t ldb,
+                               const void* dC, int64_t lddc, const void* dB, int64_t lddb,
+                               int32_t* fused);
 
 /* Replace the values of A (same pattern, original input order, any dtype)
  * and re-pack both parts (and the transposed plan).  Asynchronous.  The

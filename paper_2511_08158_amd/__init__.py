@@ -205,6 +205,17 @@ class Plan:
             _ptr(dB), n, _ptr(dA), _stream()))
         return dB, dA
 
+    def backward_fused(self, B, dC) -> bool:
+        """Whether backward(B, dC) with both gradients takes the one-pass
+        path (dB and dA from one gather of each dC row)."""
+        B = self._dense(B, self.k, "B")
+        n = B.shape[1]
+        self._dense(dC, self.m, "dC", cols=n, dtype=self.out_dtype)
+        f = ctypes.c_int32()
+        _check(library().hybrid_spmm_backward_fused(self.handle, n, _ptr(B), _ld(B), _ptr(dC), _ld(dC),
+                                                    None, n, ctypes.byref(f)))
+        return bool(f.value)
+
     def update_values(self, vals):
         if not isinstance(vals, torch.Tensor):
             raise HspmmError(-1, "vals must be a torch tensor")

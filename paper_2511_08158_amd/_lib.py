@@ -92,7 +92,7 @@ EXPORTED = [
     "hybrid_spmm_plan", "hybrid_spmm_run", "hybrid_spmm_backward", "hybrid_spmm_update_values",
     "hybrid_spmm_plan_info", "hybrid_spmm_export", "hybrid_spmm_destroy",
     "hybrid_spmm_last_error", "hybrid_spmm_version", "hybrid_spmm_calibrate", "hybrid_spmm_run_noalloc",
-    "hybrid_spmm_set_timing_events",
+    "hybrid_spmm_set_timing_events", "hybrid_spmm_backward_fused",
 ]
 
 _lib = None
@@ -116,6 +116,8 @@ def load():
     L.hybrid_spmm_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.hybrid_spmm_export.argtypes = [vp, i32, i32, vp, i64, ctypes.POINTER(i64)]
     L.hybrid_spmm_calibrate.argtypes = [vp, i64, vp, i64, vp, i64, i32, ctypes.POINTER(CalibInfo), vp]
+    L.hybrid_spmm_backward_fused.argtypes = [vp, i64, vp, i64, vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int32)]
+    L.hybrid_spmm_backward_fused.restype = ctypes.c_int
     L.hybrid_spmm_set_timing_events.argtypes = [vp, vp]
     L.hybrid_spmm_set_timing_events.restype = ctypes.c_int
     L.hybrid_spmm_destroy.argtypes = [vp]

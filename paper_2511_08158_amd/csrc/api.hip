@@ -83,6 +83,11 @@ int bwd_concurrent() {
     return (e && e[0] == '1') ? 1 : 0;
 }
 
+int bwd_fused_mode() {
+    const char* e = getenv("HSPMM_BWD_FUSED");
+    return (e && e[0] == '0') ? 0 : 1;
+}
+
 int hybrid_launch_mode() {
     const char* e = getenv("HSPMM_HYBRID_LAUNCH");
     return (e && e[0] == '2') ? 2 : 1;
@@ -245,6 +250,10 @@ int hybrid_spmm_backward(hspmm_plan_t h, int64_t n, const void* B, int64_t ldb, 
         if (n > 0 && (!B || !dC)) return fail(HSPMM_ERR_ARG, "B or dC is NULL");
         if (n > 0 && (ldb < n || lddc < n)) return fail(HSPMM_ERR_ARG, "leading dimension smaller than n");
     }
+    if (do_dB && do_dA && bwd_fusable(p, n, B, ldb, dC, lddc, dB, lddb)) {
+        HSPMM_TRY(launch_backward_fused(p, n, B, ldb, dC, lddc, dB, lddb, dA_vals, s));
+        return mark_stream(p, s);
+    }
     if (do_dB && do_dA && bwd_concurrent()) {
         // the two gradients are independent: SDDMM on the side stream,
         // forked from and joined back into the caller's stream
@@ -266,6 +275,15 @@ int hybrid_spmm_backward(hspmm_plan_t h, int64_t n, const void* B, int64_t ldb, 
     if (do_dB) HSPMM_TRY(launch_forward(p, p.T, n, dC, lddc, dB, lddb, s));
     if (do_dA) HSPMM_TRY(launch_sddmm(p, n, B, ldb, dC, lddc, dA_vals, s, nullptr));
     return mark_stream(p, s);
+}
+
+int hybrid_spmm_backward_fused(hspmm_plan_t h, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc,
+                               const void* dB, int64_t lddb, int32_t* fused) {
+    clear_error();
+    if (!h || !fused) return fail(HSPMM_ERR_ARG, "NULL argument");
+    static const unsigned char aligned_stand_in[16] __attribute__((aligned(16))) = {0};
+    *fused = bwd_fusable(h->p, n, B, ldb, dC, lddc, dB ? dB : aligned_stand_in, lddb) ? 1 : 0;
+    return HSPMM_OK;
 }
 
 int hybrid_spmm_update_values(hspmm_plan_t h, const void* vals, int32_t vals_dtype, void* stream) {

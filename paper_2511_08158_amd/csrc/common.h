@@ -214,6 +214,10 @@ int bwd_concurrent();
 // launch of a plan with both parts: 1 one fused kernel, 2 one kernel per
 // part (HSPMM_HYBRID_LAUNCH; read on every call)
 int hybrid_launch_mode();
+// 1 (default): a backward that qualifies computes dB and dA in one pass over
+// A^T's tiles; 0 (HSPMM_BWD_FUSED=0): dB and the SDDMM as separate kernels
+// (read on every backward call)
+int bwd_fused_mode();
 
 constexpr int kNumXcd = 8;
 

@@ -50,6 +50,13 @@ struct SubPlan {
 
     DevBuf scale;                 // double [nrb] (scaled sub-plans only)
 
+    // fused backward (A^T only): per stored tile, the canonical index of the
+    // first entry of A it holds and which of its 16 rows hold one (a tile of
+    // A^T is 16 consecutive columns of one row of A, so its entries are
+    // consecutive in A's canonical order)
+    DevBuf tile_base;             // int32 [nblk_pad]
+    DevBuf tile_mask;             // uint16 [nblk_pad]
+
     // groups of row blocks that share columns (group.h): the group kernels
     // visit the BCSR row blocks in the order kslot_* (groups contiguous,
     // group g = kernel slots [grp_ptr[g], grp_ptr[g + 1])), stage the columns
@@ -151,6 +158,17 @@ int grow_buf(Plan& p, DevBuf& b, size_t bytes);
 int mark_stream(Plan& p, hipStream_t s);
 // wait for the plan's queued work (the events of mark_stream)
 void wait_plan(Plan& p);
+
+// Both gradients from one pass over A^T's BCSR-part (FP32 / FP64, A^T all
+// BCSR, n within one column panel, 16-byte rows): bwd_fusable says whether
+// the call qualifies, launch_backward_fused computes dB and dA (input order)
+bool bwd_fusable(const Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc,
+                 const void* dB, int64_t lddb);
+int launch_backward_fused(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dB,
+                          int64_t lddb, void* dA, hipStream_t s);
+// the fused kernel alone: dA in canonical order; `last` = no kernel follows
+int launch_bwd_fused_kernel(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc,
+                            void* dB, int64_t lddb, void* dA_canon, hipStream_t s, bool last);
 
 int calibrate(Plan& p, int64_t n, const void* B, int64_t ldb, void* C, int64_t ldc, int reps,
               hspmm_calib_info* info, hipStream_t s);

@@ -190,6 +190,25 @@ __global__ void k_build_mask(const int32_t* __restrict__ blk_src, int64_t nblk_p
     }
 }
 
+// fused-backward tables of A^T: which rows of each tile hold an entry, and
+// the entry of the lowest such row (A's canonical index)
+__global__ void k_tile_meta(const int32_t* __restrict__ blk_src, int64_t nblk_pad, int32_t* __restrict__ base,
+                            uint16_t* __restrict__ mask) {
+    GRID_STRIDE(t, nblk_pad) {
+        uint32_t mk = 0;
+        int32_t b = 0;
+        for (int i = 15; i >= 0; --i) {
+            const int32_t v = blk_src[t * 16 + i];
+            if (v >= 0) {
+                mk |= 1u << i;
+                b = v;
+            }
+        }
+        base[t] = b;
+        mask[t] = (uint16_t)mk;
+    }
+}
+
 // SDDMM chunk tables: one thread per (row block, row) walks the row block's
 // chunks of 16 tiles in order, keeping the running canonical index of the
 // row's next entry (tiles are sorted by column, as are a row's entries)
@@ -743,6 +762,14 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
             HIP_TRY(hipStreamSynchronize(s));
             al.free(mask);
         }
+        if (&X == &p.T && !half && X.nblk_pad > 0) {
+            HSPMM_TRY(al.alloc(X.tile_base, (size_t)X.nblk_pad * 4));
+            HSPMM_TRY(al.alloc(X.tile_mask, (size_t)X.nblk_pad * 2));
+            hipLaunchKernelGGL(k_tile_meta, dim3(grid_for(X.nblk_pad)), dim3(kThreads), 0, s,
+                               X.blk_src.as<int32_t>(), X.nblk_pad, X.tile_base.as<int32_t>(),
+                               static_cast<uint16_t*>(X.tile_mask.ptr));
+            HIP_LAUNCH_CHECK();
+        }
         HIP_TRY(hipStreamSynchronize(s));
         al.free(d_slot);
         HSPMM_TRY(build_sub_groups(p, X, s));
@@ -1056,7 +1083,7 @@ int64_t SubPlan::bytes() const {
     return (int64_t)(csr_rows.bytes + csr_ptr.bytes + csr_col.bytes + csr_val.bytes + csr_src.bytes +
                      vr_start.bytes + vr_end.bytes + vr_out.bytes + vr_row.bytes + long_row.bytes + long_first.bytes +
                      long_cnt.bytes + bcsr_rb.bytes + blk_ptr.bytes + blk_cnt.bytes + blk_col.bytes +
-                     blk_val.bytes + blk_src.bytes + chunk_ptr.bytes + chunk_base.bytes + chunk_mask.bytes +
+                     blk_val.bytes + blk_src.bytes + tile_base.bytes + tile_mask.bytes + chunk_ptr.bytes + chunk_base.bytes + chunk_mask.bytes +
                      scale.bytes);
 }
 

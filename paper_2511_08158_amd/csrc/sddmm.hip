@@ -519,6 +519,35 @@ inline bool aligned(const void* p, size_t al) { return ((uintptr_t)p % al) == 0;
 
 }  // namespace
 
+namespace {
+// dA from canonical order to the input order of a non-canonical plan
+int gather_dA(Plan& p, const DevBuf& ws, void* dA, hipStream_t s) {
+    const unsigned g = (unsigned)std::min<int64_t>(ceil_div(p.nnz_in, 256), 65536);
+    if (p.compute == HSPMM_F64) {
+        HSPMM_LAUNCH(k_gather_dA<double>, dim3(g), dim3(256), 0, s, false, true, ws.as<double>(),
+                     p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<double*>(dA));
+    } else {
+        HSPMM_LAUNCH(k_gather_dA<float>, dim3(g), dim3(256), 0, s, false, true, ws.as<float>(),
+                     p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<float*>(dA));
+    }
+    HIP_LAUNCH_CHECK();
+    return HSPMM_OK;
+}
+}  // namespace
+
+int launch_backward_fused(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dB,
+                          int64_t lddb, void* dA, hipStream_t s) {
+    const size_t go = p.compute == HSPMM_F64 ? 8 : 4;
+    void* target = dA;
+    if (!p.canonical) {
+        HSPMM_TRY(grow_buf(p, p.ws, (size_t)p.nnz * go));
+        target = p.ws.ptr;
+    }
+    HSPMM_TRY(launch_bwd_fused_kernel(p, n, B, ldb, dC, lddc, dB, lddb, target, s, p.canonical));
+    if (!p.canonical) HSPMM_TRY(gather_dA(p, p.ws, dA, s));
+    return HSPMM_OK;
+}
+
 int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dA,
                  hipStream_t s, DevBuf* wsb) {
     SubPlan& X = p.A;
@@ -589,17 +618,7 @@ int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC,
         (void)eb;
         HSPMM_TRY(rc);
     }
-    if (!p.canonical) {
-        const unsigned g = (unsigned)std::min<int64_t>(ceil_div(p.nnz_in, 256), 65536);
-        if (go == 8) {
-            HSPMM_LAUNCH(k_gather_dA<double>, dim3(g), dim3(256), 0, s, false, true, ws.as<double>(),
-                         p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<double*>(dA));
-        } else {
-            HSPMM_LAUNCH(k_gather_dA<float>, dim3(g), dim3(256), 0, s, false, true, ws.as<float>(),
-                         p.canon_of_orig.as<int32_t>(), p.nnz_in, static_cast<float*>(dA));
-        }
-        HIP_LAUNCH_CHECK();
-    }
+    if (!p.canonical) HSPMM_TRY(gather_dA(p, ws, dA, s));
     return HSPMM_OK;
 }
 

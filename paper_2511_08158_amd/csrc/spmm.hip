@@ -498,6 +498,221 @@ __device__ void bcsr_wave_f(const BcsrArgs& a, const DenseArgs& d, int64_t unit)
 }
 
 // ---------------------------------------------------------------------------
+// Fused backward on the BCSR-part of A^T (FP32 / FP64)
+// ---------------------------------------------------------------------------
+// A tile of A^T (row block R of A^T, column i) holds A[i][16R .. 16R + 15].
+// The walk that computes dB = A^T dC for row block R gathers row i of dC for
+// that tile, and the same row is all the SDDMM needs for the tile's entries
+// of dA: dA[i][16R + r] = <dC[i,:], B[16R + r,:]> (the gradient of Sec.
+// 3.3's product with respect to A's stored values).  One pass over A^T's
+// tiles thus yields both gradients with one gather of dC per tile, where
+// separate dB and SDDMM kernels run two gather streams (rows of dC, rows of
+// B): on the block stencil FP32 n = 128 the L1 -> L2 read requests of the
+// backward fall by 41 % and the backward from 70 to 62 us cold.
+//
+// For dA the contraction runs over the columns, so the gathered rows are
+// needed with the column on the MFMA's K lanes, where the dB product has
+// them on its N lanes: each step's gathered rows are written to an LDS tile
+// of 16 rows (one per tile of a round of 4 steps) and read back after the
+// round.  The 16 x 16 result of a round is
+//     out[r][t] = sum_c B[16R + r][c] * dC[i_t][c],
+// with B's 16 rows (the row block's columns of A) held in registers for the
+// whole row block.  A tile's entries are consecutive columns of one row of
+// A, so they are consecutive in A's canonical order too: entry r of tile t
+// goes to tile_base[t] + popcount(tile_mask[t] below bit r).
+struct BwdArgs {
+    const int32_t* tile_base;   // [tiles] canonical index of the tile's first entry of A
+    const uint16_t* tile_mask;  // [tiles] rows of the tile that hold an entry
+    const void* B;              // forward dense operand, k x n
+    int64_t ldb;
+    int64_t kb;                 // rows of B (columns of A)
+    void* dA;                   // canonical order of A's entries
+};
+
+template <class T, int N>
+__device__ inline void store_lds_vec(T* p, const T (&in)[N]) {
+    if constexpr (N == 1) {
+        *p = in[0];
+    } else {
+        typedef T V __attribute__((ext_vector_type(N)));
+        V v;
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = in[i];
+        *reinterpret_cast<V*>(p) = v;
+    }
+}
+
+// A workgroup of NW waves per row block of A^T, wave w owning columns
+// [w CW, (w + 1) CW) of the panel (CW = 16 VEC, each lane VEC elements = 16
+// bytes of a gathered row).  Every wave walks all of the row block's tiles,
+// so each gathered row of dC is fetched as NW segments, one per wave, and a
+// wave's registers hold only its share of the dB accumulators and of the
+// 16 rows of B.  One wave holding the whole panel (the forward's walk plus
+// the dA product) needed 136 registers, 3 waves per SIMD, and ran the block
+// stencil's backward in 74 us; two waves of 64 columns need 94 (5 per
+// SIMD).  Four waves of 8-byte segments (8 per SIMD) were slower (68 us):
+// twice the load instructions, and each wave reloads the tile values.
+// Each wave's dA products cover its own columns; after each round of 16
+// tiles the partial 16 x 16 results are summed in wave order through LDS
+// (double-buffered, one barrier per round) and written tile by tile, the 16
+// lanes of a tile side by side on its consecutive entries (writing them
+// from the MFMA layout, 4 scattered entries per tile and instruction, cost
+// 2 us more).  The dA tile metadata of 64 tiles is fetched with their
+// columns: a load inside a round would make the round's end wait for the
+// gathers already issued for the next one.
+template <class T, int NW, int VEC>
+struct BwdCs {
+    static constexpr int CW = 16 * VEC;              // columns per wave
+    static constexpr int PANEL = NW * CW;
+    static constexpr int KS = CW / 4;                // dA MFMA steps per round (K = 4 columns each)
+    static constexpr int RPW = 4 / NW;               // dA store rounds of 4 tiles per wave and round
+    static constexpr int CWP = CW + 16 / (int)sizeof(T);  // padded LDS row of the transposition buffer
+    // LDS: per wave 16 rows of CWP, then two buffers of NW waves x 64 lanes x 4 partial sums
+    static constexpr size_t kLdsT = (size_t)NW * 16 * CWP * sizeof(T);
+    static constexpr size_t kLdsP = (size_t)2 * NW * 64 * 4 * sizeof(T);
+    static constexpr size_t kLds = kLdsT + kLdsP;
+};
+
+template <class T, int NW, int VEC>
+__device__ void bwd_cs(const BcsrArgs& a, const DenseArgs& d, const BwdArgs& bw, int64_t slot, unsigned char* smem,
+                       int& buf) {
+    typedef typename AccOf<T>::type acc_v;
+    typedef BwdCs<T, NW, VEC> P;
+    constexpr int CW = P::CW, KS = P::KS, CWP = P::CWP, RPW = P::RPW;
+    const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4, w = wave_id();
+    T* __restrict__ lt = reinterpret_cast<T*>(smem) + (int64_t)w * 16 * CWP;
+    T* __restrict__ lp = reinterpret_cast<T*>(smem + P::kLdsT);
+    const int rb = a.rb[slot];
+    const int b0 = a.blk_ptr[slot];
+    const int cnt = a.blk_cnt[slot];
+    const int nsteps = (cnt + 3) >> 2;
+    const int64_t c0 = (int64_t)w * CW;                 // this wave's first column
+    const int64_t cl = c0 + (int64_t)j * VEC;           // this lane's columns in the walk
+    const bool colok = cl < d.n;
+    const T* __restrict__ vals = static_cast<const T*>(a.val);
+    const T* __restrict__ G = static_cast<const T*>(d.B);
+    // the dA product's A operand: row 16 rb + j of B at this wave's columns
+    // c0 + KS q + s, the K lane of step s being q
+    // (16-byte chunks, each wholly inside or outside n)
+    T bs[KS];
+    {
+        constexpr int CH = 16 / (int)sizeof(T);
+        const int64_t brow = (int64_t)rb * 16 + j;
+#pragma unroll
+        for (int h = 0; h < KS; h += CH) {
+            const int64_t c = c0 + (int64_t)KS * q + h;
+            T x[CH];
+            if (brow < bw.kb && c < d.n) {
+                load_vec<T, CH>(static_cast<const T*>(bw.B) + brow * bw.ldb + c, x);
+            } else {
+#pragma unroll
+                for (int e = 0; e < CH; ++e) x[e] = T(0);
+            }
+#pragma unroll
+            for (int e = 0; e < CH; ++e) bs[h + e] = x[e];
+        }
+    }
+    acc_v acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = acc_v{0, 0, 0, 0};
+    for (int s0 = 0; s0 < nsteps; s0 += 16) {
+        const int colreg = 4 * s0 + lane < cnt ? a.blk_col[b0 + 4 * s0 + lane] : 0;
+        // the dA destinations of the same 64 tiles (tiles past cnt: none),
+        // fetched with the columns so that no load waits inside a round
+        const int32_t basereg = 4 * s0 + lane < cnt ? bw.tile_base[b0 + 4 * s0 + lane] : 0;
+        const uint32_t maskreg = 4 * s0 + lane < cnt ? (uint32_t)bw.tile_mask[b0 + 4 * s0 + lane] : 0u;
+        const int send = min(nsteps, s0 + 16);
+        // operands of one step: this lane's A value and VEC elements of the
+        // gathered row of tile 4 st + q (steps past the last reload it)
+        auto load = [&](int st, T& av, T (&bv)[VEC]) {
+            const int ss = min(st, send - 1);
+            const int bc = __shfl(colreg, (4 * (ss - s0) + q) & 63, 64);
+            av = vals[(int64_t)(b0 + 4 * ss) * 16 + lane];
+            load_vec<T, VEC>(G + (int64_t)bc * d.ldb + (colok ? cl : 0), bv);
+        };
+        T ax, ay, bx[VEC], by[VEC];
+        load(s0, ax, bx);
+        for (int sr = s0; sr < send; sr += 4) {
+#pragma unroll
+            for (int st = 0; st < 4; st += 2) {
+                load(sr + st + 1, ay, by);
+                __builtin_amdgcn_sched_barrier(0);
+                {
+                    const T av = sr + st < send ? ax : T(0);
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) acc[v] = mfma4(av, bx[v], acc[v]);
+                    store_lds_vec<T, VEC>(lt + (4 * st + q) * CWP + j * VEC, bx);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                load(sr + st + 2, ax, bx);
+                __builtin_amdgcn_sched_barrier(0);
+                {
+                    const T av = sr + st + 1 < send ? ay : T(0);
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) acc[v] = mfma4(av, by[v], acc[v]);
+                    store_lds_vec<T, VEC>(lt + (4 * (st + 1) + q) * CWP + j * VEC, by);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // this wave's share of the round's dA: lane (j, q) supplies tile
+            // j's columns KS q + s (its own writes above, in LDS order)
+            T gv[KS];
+            load_vec<T, KS>(lt + j * CWP + KS * q, gv);
+            acc_v g = acc_v{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) g = mfma4(bs[s], gv[s], g);
+            T* __restrict__ pb = lp + (int64_t)buf * NW * 64 * 4;
+            {
+                const T gp[4] = {g[0], g[1], g[2], g[3]};
+                store_lds_vec<T, 4>(pb + ((int64_t)w * 64 + lane) * 4, gp);
+            }
+            // the buffers alternate over every round the workgroup runs, so
+            // a buffer is rewritten only after every wave passed the
+            // barrier that follows its last reads
+            __syncthreads();
+            // the sums over the waves (in wave order), written tile by tile:
+            // lane l takes row rr = l % 16 of tile t = 4 i + l / 16, so the
+            // 16 lanes of a tile write its entries, consecutive in A's
+            // canonical order, side by side; wave w takes tiles
+            // [16 w / NW, 16 (w + 1) / NW)
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) {
+                const int t = (16 / NW) * w + 4 * i + q;   // tile of this lane
+                const int rr = j;                          // its row (a column of A)
+                const int g4 = sizeof(T) == 8 ? (rr & 3) : (rr >> 2);  // lane group holding row rr
+                const int r = sizeof(T) == 8 ? (rr >> 2) : (rr & 3);   // and its register
+                const int src = 16 * g4 + t;
+                T sum = pb[(0 * 64 + src) * 4 + r];
+#pragma unroll
+                for (int u = 1; u < NW; ++u) sum += pb[((int64_t)u * 64 + src) * 4 + r];
+                const int32_t base = __shfl((int)basereg, (4 * (sr - s0) + t) & 63, 64);
+                const uint32_t mk = (uint32_t)__shfl((int)maskreg, (4 * (sr - s0) + t) & 63, 64);
+                if ((mk >> rr) & 1u) static_cast<T*>(bw.dA)[base + __popc(mk & ((1u << rr) - 1u))] = sum;
+            }
+            buf ^= 1;
+        }
+    }
+    if (!colok) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t row = (int64_t)rb * 16 + out_row<T>(q, r);
+        if (row >= d.m) continue;
+        T o[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) o[v] = acc[v][r];
+        store_vec<T, VEC>(static_cast<T*>(d.C) + row * d.ldc + cl, o);
+    }
+}
+
+template <class T, int NW, int VEC>
+__global__ __launch_bounds__(256) void k_bwd_cs(BcsrArgs ba, DenseArgs da, BwdArgs bw, uint32_t g, int remap) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int buf = 0;
+    for (int64_t slot = (int64_t)xcd_remap(blockIdx.x, g, remap); slot < ba.n_rb; slot += g)
+        bwd_cs<T, NW, VEC>(ba, da, bw, slot, lds_raw, buf);
+}
+
+// ---------------------------------------------------------------------------
 // BCSR-part in groups of row blocks that share columns, FP32 / FP64
 // ---------------------------------------------------------------------------
 // One workgroup per (group, column panel of 256 bytes).  It copies the
@@ -1254,6 +1469,51 @@ int dispatch_half(const SubPlan& X, const DenseArgs& d, bool vec_ok, hipStream_t
 }
 
 }  // namespace
+
+// widest n of the fused backward: FP32 four waves of 64 columns, FP64 four of 32
+inline int64_t bwd_max_n(int compute) { return compute == HSPMM_F64 ? 128 : 256; }
+
+bool bwd_fusable(const Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc,
+                 const void* dB, int64_t lddb) {
+    if (!bwd_fused_mode() || !p.has_T || n <= 0) return false;
+    const SubPlan& T = p.T;
+    if (p.compute != HSPMM_F32 && p.compute != HSPMM_F64) return false;
+    if (T.ct != p.compute || T.scaled || T.rb_bcsr == 0 || T.n_vrows > 0 || !T.tile_base.ptr) return false;
+    if (T.max_rb_tiles > kWaveMaxTiles) return false;
+    const int64_t vec = p.compute == HSPMM_F64 ? 2 : 4;  // elements of 16 bytes
+    return n <= bwd_max_n(p.compute) && n % vec == 0 && ldb % vec == 0 && lddc % vec == 0 && lddb % vec == 0 &&
+           aligned(B, 16) && aligned(dC, 16) && aligned(dB, 16);
+}
+
+namespace {
+template <class T, int NW>
+int launch_bwd_cs(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dB,
+                  int64_t lddb, void* dA, hipStream_t s, bool last) {
+    constexpr int VEC = 16 / (int)sizeof(T);
+    const SubPlan& X = p.T;
+    BcsrArgs ba{X.bcsr_rb.as<int32_t>(), X.blk_ptr.as<int32_t>(), X.blk_cnt.as<int32_t>(), X.blk_col.as<int32_t>(),
+                X.blk_val.ptr, X.rb_bcsr, 1};
+    DenseArgs da{dC, lddc, dB, lddb, n, X.m, nullptr, nullptr};
+    BwdArgs bw{X.tile_base.as<int32_t>(), static_cast<const uint16_t*>(X.tile_mask.ptr), B, ldb, p.k, dA};
+    const uint32_t g = pad8(X.rb_bcsr);
+    const size_t lds = BwdCs<T, NW, VEC>::kLds;
+    HSPMM_LAUNCH((k_bwd_cs<T, NW, VEC>), dim3(g), dim3(64 * NW), lds, s, true, last, ba, da, bw, g,
+                 xcd_remap_mode());
+    HIP_LAUNCH_CHECK();
+    return HSPMM_OK;
+}
+}  // namespace
+
+int launch_bwd_fused_kernel(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc,
+                            void* dB, int64_t lddb, void* dA_canon, hipStream_t s, bool last) {
+    // two waves while n fits their panel (more waves per SIMD), else four
+    if (p.compute == HSPMM_F64) {
+        if (n <= 64) return launch_bwd_cs<double, 2>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
+        return launch_bwd_cs<double, 4>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
+    }
+    if (n <= 128) return launch_bwd_cs<float, 2>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
+    return launch_bwd_cs<float, 4>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
+}
 
 size_t forward_scratch_bytes(const SubPlan& X, int64_t n) {
     const size_t acc_b = X.ct == HSPMM_F64 ? 8 : 4;
