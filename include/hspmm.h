@@ -177,15 +177,20 @@ int hybrid_spmm_run_noalloc(hspmm_plan_t p, int64_t n, const void* B, int64_t ld
  * multiple of 8, at most 256) first round each 16-row slab of dC to the
  * compute type after an exact power-of-two scale (largest magnitude in
  * [2^14, 2^15)), one rounding per dC element.
- * When both gradients are requested, an F32/F64 plan whose transposed plan
- * is all BCSR-part computes them in one pass over the tiles of A^T: each
- * tile's gathered row of dC serves its dB product and its entries' dA dot
- * products (Sec. 3.3 product and its gradient; one gather stream instead of
- * two), for n up to 256 (FP32) / 128 (FP64) with n, ldb, lddc, lddb
- * multiples of 16 bytes and 16-byte aligned B, dC, dB.
- * dB is then bitwise the separate product's; dA differs only in summation
- * order.  Errors: ARG, NO_BACKWARD (dB requested without want_backward),
- * HIP, OOM. */
+ * When both gradients are requested, they are computed in one pass over
+ * the transposed plan: each gathered row of dC serves its dB product and
+ * the dA dot products of the same entries (Sec. 3.3 product and its
+ * gradient; one gather stream instead of two).  This applies for n up to
+ * 256 (FP32 dC) / 128 (FP64) with n, ldb, lddc, lddb multiples of 16 bytes
+ * and 16-byte aligned dC, dB, B (8-byte B for F16/BF16 plans); a
+ * BCSR-part in A^T qualifies for F32/F64 plans only (its dA
+ * MFMAs hold B in the compute type) and with at most 2048 tiles per row
+ * block, a CSR-part from rows of B of 256 bytes (n * element size; below
+ * that the separate SDDMM's own gathers cost less than the one-pass form's
+ * scattered dA writes).  dB is then bitwise the separate product's; dA differs only in
+ * summation order, and for F16/BF16 plans its dot products run in FP32
+ * on the stored B (no rounding of dC).  Errors: ARG, NO_BACKWARD (dB
+ * requested without want_backward), HIP, OOM. */
 int hybrid_spmm_backward(hspmm_plan_t p, int64_t n, const void* B, int64_t ldb,
                          const void* dC, int64_t lddc, void* dB, int64_t lddb,
                          void* dA_vals, void* stream);

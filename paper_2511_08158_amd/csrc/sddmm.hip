@@ -539,12 +539,13 @@ int launch_backward_fused(Plan& p, int64_t n, const void* B, int64_t ldb, const 
                           int64_t lddb, void* dA, hipStream_t s) {
     const size_t go = p.compute == HSPMM_F64 ? 8 : 4;
     void* target = dA;
+    // (the plan's first scratch buffer may hold A^T's split-row partials)
     if (!p.canonical) {
-        HSPMM_TRY(grow_buf(p, p.ws, (size_t)p.nnz * go));
-        target = p.ws.ptr;
+        HSPMM_TRY(grow_buf(p, p.ws2, (size_t)p.nnz * go));
+        target = p.ws2.ptr;
     }
     HSPMM_TRY(launch_bwd_fused_kernel(p, n, B, ldb, dC, lddc, dB, lddb, target, s, p.canonical));
-    if (!p.canonical) HSPMM_TRY(gather_dA(p, p.ws, dA, s));
+    if (!p.canonical) HSPMM_TRY(gather_dA(p, p.ws2, dA, s));
     return HSPMM_OK;
 }
 

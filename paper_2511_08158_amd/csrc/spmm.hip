@@ -712,6 +712,148 @@ __global__ __launch_bounds__(256) void k_bwd_cs(BcsrArgs ba, DenseArgs da, BwdAr
         bwd_cs<T, NW, VEC>(ba, da, bw, slot, lds_raw, buf);
 }
 
+// CSR-part of A^T in the fused backward: LPR lanes per (segment of a) row
+// j of A^T, which is column j of A, each lane VEC columns of one panel.
+// Row j of B sits in the lane group's registers; every entry (i, a_ij)
+// gathers row i of dC once, adds a_ij dC[i,:] to the row of dB (in entry
+// order, as the forward's CSR walk sums) and forms the lane's share of
+// dA[i][j] = <dC[i,:], B[j,:]>, reduced across the group U entries at a
+// time by a halving butterfly (U - 1 + log2(LPR / U) shuffles per U
+// entries).  dA goes to A's canonical index of the entry.
+struct CsrBwdArgs {
+    const int32_t* vr_start;
+    const int32_t* vr_end;
+    const int32_t* vr_out;   // row of dB, or -(partial slot + 1) of a split row
+    const int32_t* vr_row;   // row of A^T
+    const int32_t* col;      // row of A
+    const void* val;         // values of A^T (the dC type)
+    const int32_t* dst;      // A's canonical index of each entry
+    int64_t n_vrows;
+    const void* B;           // forward dense operand (compute type)
+    int64_t ldb;
+    void* dA;
+};
+
+// entries reduced together (U) and gathers in flight (UB): 8 / 4 against
+// 16 / 8 (137 -> 94 registers at 32 lanes) measured GCN FP32 n = 128
+// backward 837 -> 823 us, power law FP16 n = 128 1490 -> 1487; 4 / 4 was
+// within 3 % either way
+#ifndef HSPMM_BWD_CSR_U
+#define HSPMM_BWD_CSR_U 8
+#endif
+#ifndef HSPMM_BWD_CSR_UB
+#define HSPMM_BWD_CSR_UB 4
+#endif
+template <class TB, class TG, int VEC, int LPR>
+__device__ void csr_bwd_wave(const CsrBwdArgs& a, const DenseArgs& d, int64_t wave) {
+    constexpr int R = 64 / LPR;
+    constexpr int U = LPR < HSPMM_BWD_CSR_U ? LPR : HSPMM_BWD_CSR_U;
+    constexpr int SPAN = LPR / U;  // lanes that end with the same entry
+    constexpr int UB = U < HSPMM_BWD_CSR_UB ? U : HSPMM_BWD_CSR_UB;  // gathers in flight
+    const int lane = threadIdx.x & 63;
+    const int g = lane / LPR, gl = lane % LPR;
+    if (wave * R >= a.n_vrows) return;  // wave-uniform
+    const int64_t vr = wave * R + g;
+    const bool act = vr < a.n_vrows;
+    const int start = act ? a.vr_start[vr] : 0;
+    const int len = act ? a.vr_end[vr] - start : 0;
+    const int out = act ? a.vr_out[vr] : 0;
+    const int row = act ? a.vr_row[vr] : 0;
+    int maxlen = len;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o, 64));
+    const TG* __restrict__ val = static_cast<const TG*>(a.val);
+    const TG* __restrict__ dC = static_cast<const TG*>(d.B);
+    TG* __restrict__ dA = static_cast<TG*>(a.dA);
+    const int64_t col0 = (int64_t)gl * VEC;
+    const bool colok = col0 < d.n;
+    TG b0[VEC];
+    {
+        TB x[VEC];
+        if (act && colok) {
+            load_vec<TB, VEC>(static_cast<const TB*>(a.B) + (int64_t)row * a.ldb + col0, x);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) x[v] = TB(0);
+        }
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) b0[v] = Elem<TB>::to_acc(x[v]);
+    }
+    TG acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = TG(0);
+    for (int base = 0; base < maxlen; base += LPR) {
+        const bool eok = base + gl < len;
+        const int e = start + base + gl;
+        const int my_col = eok ? a.col[e] : -1;
+        const TG my_val = eok ? val[e] : TG(0);
+        const int my_dst = eok ? a.dst[e] : -1;
+        const int cnt = min(LPR, maxlen - base);
+        for (int u0 = 0; u0 < cnt; u0 += U) {
+            TG part[U];
+#pragma unroll
+            for (int ub = 0; ub < U; ub += UB) {
+                // branch-free gathers: an absent entry or a lane past n
+                // reads row 0 / column 0 and a select drops its products
+                TG cv[UB][VEC];
+                TG vv[UB];
+                bool ok[UB];
+#pragma unroll
+                for (int k = 0; k < UB; ++k) {
+                    const int c = __shfl(my_col, (u0 + ub + k) & (LPR - 1), LPR);
+                    vv[k] = __shfl(my_val, (u0 + ub + k) & (LPR - 1), LPR);
+                    ok[k] = c >= 0 && u0 + ub + k < cnt && colok;
+                    load_vec<TG, VEC>(dC + (int64_t)(ok[k] ? c : 0) * d.ldb + (colok ? col0 : 0), cv[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < UB; ++k) {
+                    TG dot = TG(0);
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        acc[v] += vv[k] * (ok[k] ? cv[k][v] : TG(0));
+                        dot += b0[v] * cv[k][v];
+                    }
+                    part[ub + k] = ok[k] ? dot : TG(0);
+                }
+            }
+            // halving butterfly over the offsets LPR/2 .. SPAN
+#pragma unroll
+            for (int nv = U, o = LPR / 2; nv > 1; nv >>= 1, o >>= 1) {
+                const bool up = (gl & o) != 0;
+#pragma unroll
+                for (int i = 0; i < nv / 2; ++i) {
+                    const TG keep = up ? part[i + nv / 2] : part[i];
+                    const TG send = up ? part[i] : part[i + nv / 2];
+                    part[i] = keep + __shfl_xor(send, o, LPR);
+                }
+            }
+#pragma unroll
+            for (int o = SPAN / 2; o >= 1; o >>= 1) part[0] += __shfl_xor(part[0], o, LPR);
+            const int idx = u0 + gl / SPAN;
+            const int dd = __shfl(my_dst, idx & (LPR - 1), LPR);
+            if ((gl % SPAN) == 0 && idx < cnt && dd >= 0) dA[dd] = part[0];
+        }
+    }
+    if (act && colok) {
+        if (out >= 0) {
+            store_vec<TG, VEC>(static_cast<TG*>(d.C) + (int64_t)out * d.ldc + col0, acc);
+        } else {
+            TG* ws = static_cast<TG*>(d.ws) + (int64_t)(-out - 1) * d.n + col0;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) ws[v] = acc[v];
+        }
+    }
+}
+
+template <class TB, class TG, int VEC, int LPR>
+__global__ __launch_bounds__(256) void k_bwd_csr(CsrBwdArgs a, DenseArgs d, uint32_t g, int remap) {
+    constexpr int R = 64 / LPR;
+    const int64_t waves = (a.n_vrows + R - 1) / R;
+    for (int64_t wave = (int64_t)xcd_remap(blockIdx.x, g, remap) * 4 + wave_id(); wave < waves;
+         wave += (int64_t)g * 4)
+        csr_bwd_wave<TB, TG, VEC, LPR>(a, d, wave);
+}
+
 // ---------------------------------------------------------------------------
 // BCSR-part in groups of row blocks that share columns, FP32 / FP64
 // ---------------------------------------------------------------------------
@@ -1470,49 +1612,115 @@ int dispatch_half(const SubPlan& X, const DenseArgs& d, bool vec_ok, hipStream_t
 
 }  // namespace
 
-// widest n of the fused backward: FP32 four waves of 64 columns, FP64 four of 32
-inline int64_t bwd_max_n(int compute) { return compute == HSPMM_F64 ? 128 : 256; }
+// widest n of the fused backward: FP32 four waves (BCSR-part) or 64 lanes
+// (CSR-part) of 16-byte segments, FP64 the same at half the columns
+inline int64_t bwd_max_n(int ct) { return ct == HSPMM_F64 ? 128 : 256; }
 
 bool bwd_fusable(const Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc,
                  const void* dB, int64_t lddb) {
     if (!bwd_fused_mode() || !p.has_T || n <= 0) return false;
     const SubPlan& T = p.T;
-    if (p.compute != HSPMM_F32 && p.compute != HSPMM_F64) return false;
-    if (T.ct != p.compute || T.scaled || T.rb_bcsr == 0 || T.n_vrows > 0 || !T.tile_base.ptr) return false;
-    if (T.max_rb_tiles > kWaveMaxTiles) return false;
-    const int64_t vec = p.compute == HSPMM_F64 ? 2 : 4;  // elements of 16 bytes
-    return n <= bwd_max_n(p.compute) && n % vec == 0 && ldb % vec == 0 && lddc % vec == 0 && lddb % vec == 0 &&
-           aligned(B, 16) && aligned(dC, 16) && aligned(dB, 16);
+    const bool has_b = T.rb_bcsr > 0, has_c = T.n_vrows > 0;
+    if (T.scaled || (!has_b && !has_c)) return false;
+    const int64_t vec = T.ct == HSPMM_F64 ? 2 : 4;  // elements of dC in 16 bytes
+    if (n > bwd_max_n(T.ct) || n % vec != 0 || ldb % vec != 0 || lddc % vec != 0 || lddb % vec != 0 ||
+        !aligned(dC, 16) || !aligned(dB, 16))
+        return false;
+    // the BCSR-part form holds B's rows in the compute type of its MFMAs:
+    // FP32 / FP64 plans only, with 16-byte rows
+    if (has_b && (p.compute != T.ct || !T.tile_base.ptr || T.max_rb_tiles > kWaveMaxTiles || !aligned(B, 16)))
+        return false;
+    // the CSR-part form saves the SDDMM's gather of a row of B per entry
+    // but writes each entry's dA on its own (the entries of a row of A^T
+    // lie in different rows of A) and adds a reduction across the lane
+    // group: measured (backward, us, fused / separate) GCN FP32 n = 64
+    // 543 / 671, n = 128 823 / 1336, FP16 n = 128 830 / 1007; power law
+    // FP32 n = 64 991 / 1150, FP16 n = 128 1511 / 1726, but FP16 n = 64
+    // (rows of 128 bytes) 991 / 921: it is taken from 256-byte rows of B
+    if (has_c && n * (int64_t)dtype_size(p.compute) < 256) return false;
+    return aligned(B, (size_t)vec * dtype_size(p.compute));
 }
 
 namespace {
 template <class T, int NW>
-int launch_bwd_cs(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dB,
-                  int64_t lddb, void* dA, hipStream_t s, bool last) {
+int launch_bwd_cs(Plan& p, int64_t n, const void* B, int64_t ldb, const DenseArgs& da, void* dA, hipStream_t s,
+                  bool first, bool last) {
     constexpr int VEC = 16 / (int)sizeof(T);
     const SubPlan& X = p.T;
     BcsrArgs ba{X.bcsr_rb.as<int32_t>(), X.blk_ptr.as<int32_t>(), X.blk_cnt.as<int32_t>(), X.blk_col.as<int32_t>(),
                 X.blk_val.ptr, X.rb_bcsr, 1};
-    DenseArgs da{dC, lddc, dB, lddb, n, X.m, nullptr, nullptr};
     BwdArgs bw{X.tile_base.as<int32_t>(), static_cast<const uint16_t*>(X.tile_mask.ptr), B, ldb, p.k, dA};
     const uint32_t g = pad8(X.rb_bcsr);
     const size_t lds = BwdCs<T, NW, VEC>::kLds;
-    HSPMM_LAUNCH((k_bwd_cs<T, NW, VEC>), dim3(g), dim3(64 * NW), lds, s, true, last, ba, da, bw, g,
+    HSPMM_LAUNCH((k_bwd_cs<T, NW, VEC>), dim3(g), dim3(64 * NW), lds, s, first, last, ba, da, bw, g,
                  xcd_remap_mode());
     HIP_LAUNCH_CHECK();
+    return HSPMM_OK;
+}
+
+template <class TB, class TG>
+int launch_bwd_csr(Plan& p, int64_t n, const void* B, int64_t ldb, const DenseArgs& da, void* dA, hipStream_t s,
+                   bool first, bool last) {
+    constexpr int VEC = 16 / (int)sizeof(TG);
+    const SubPlan& X = p.T;
+    CsrBwdArgs ca{X.vr_start.as<int32_t>(), X.vr_end.as<int32_t>(), X.vr_out.as<int32_t>(), X.vr_row.as<int32_t>(),
+                  X.csr_col.as<int32_t>(), X.csr_val.ptr, X.csr_src.as<int32_t>(), X.n_vrows, B, ldb, dA};
+    const int rm = xcd_remap_mode();
+    HSPMM_LPR_SWITCH(lpr_for(n, VEC), {
+        constexpr int R = 64 / LPR;
+        const uint32_t g = pad8(ceil_div(ceil_div(X.n_vrows, R), 4));
+        HSPMM_LAUNCH((k_bwd_csr<TB, TG, VEC, LPR>), dim3(g), dim3(256), 0, s, first, last, ca, da, g, rm);
+    });
+    HIP_LAUNCH_CHECK();
+    return HSPMM_OK;
+}
+
+template <class TB, class TG>
+int launch_bwd_parts(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dB,
+                     int64_t lddb, void* dA, hipStream_t s, bool last) {
+    SubPlan& X = p.T;
+    // partial rows of split CSR rows of A^T (every slot written before the
+    // reduction reads it)
+    void* ws = nullptr;
+    if (X.n_partials > 0) {
+        HSPMM_TRY(ensure_ws(p, forward_scratch_bytes(X, n)));
+        ws = p.ws.ptr;
+    }
+    DenseArgs da{dC, lddc, dB, lddb, n, X.m, ws, nullptr};
+    const bool has_b = X.rb_bcsr > 0, has_c = X.n_vrows > 0, has_l = X.n_long > 0;
+    if (has_b) {
+        if constexpr (std::is_same<TB, TG>::value) {
+            // two waves while n fits their panel (more waves per SIMD), else four
+            const bool two = n <= 2 * 16 * (16 / (int64_t)sizeof(TG));
+            const bool l = last && !has_c && !has_l;
+            const int rc = two ? launch_bwd_cs<TG, 2>(p, n, B, ldb, da, dA, s, true, l)
+                               : launch_bwd_cs<TG, 4>(p, n, B, ldb, da, dA, s, true, l);
+            HSPMM_TRY(rc);
+        } else {
+            return fail(HSPMM_ERR_ARG, "fused backward: BCSR-part of a low-precision plan");
+        }
+    }
+    if (has_c) {
+        const int rc = launch_bwd_csr<TB, TG>(p, n, B, ldb, da, dA, s, !has_b, last && !has_l);
+        HSPMM_TRY(rc);
+    }
+    if (has_l) {
+        launch_long_reduce<TG, TG>(X, da, s);
+        HIP_LAUNCH_CHECK();
+    }
     return HSPMM_OK;
 }
 }  // namespace
 
 int launch_bwd_fused_kernel(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc,
                             void* dB, int64_t lddb, void* dA_canon, hipStream_t s, bool last) {
-    // two waves while n fits their panel (more waves per SIMD), else four
-    if (p.compute == HSPMM_F64) {
-        if (n <= 64) return launch_bwd_cs<double, 2>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
-        return launch_bwd_cs<double, 4>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
+    switch (p.compute) {
+        case HSPMM_F64: return launch_bwd_parts<double, double>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
+        case HSPMM_F32: return launch_bwd_parts<float, float>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
+        case HSPMM_F16: return launch_bwd_parts<half_t, float>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
+        case HSPMM_BF16: return launch_bwd_parts<bf16_t, float>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
+        default: return fail(HSPMM_ERR_DTYPE, "bad compute dtype");
     }
-    if (n <= 128) return launch_bwd_cs<float, 2>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
-    return launch_bwd_cs<float, 4>(p, n, B, ldb, dC, lddc, dB, lddb, dA_canon, s, last);
 }
 
 size_t forward_scratch_bytes(const SubPlan& X, int64_t n) {
