@@ -75,7 +75,9 @@ __device__ inline void load_vec(const T* p, T (&out)[N]) {
 // non-temporal, the output being written once and never read by the kernel
 // (so that it would not displace gathered rows of B from L2): measured on
 // the block stencil FP32 forward 37.2 against 38.4 us warm but 43.2 against
-// 42.6 us cold, so it is off.
+// 42.6 us cold, and over whole steps (forward and one-pass backward, with
+// its dA stores non-temporal too) 96.6 against 98.5 us warm but 111.2
+// against 109.5 us cold, so it is off.
 #ifndef HSPMM_NT_STORE
 #define HSPMM_NT_STORE 0
 #endif
