@@ -33,7 +33,12 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
 
 void DevBuf::release() {
     if (ptr) {
-        (void)hipFree(ptr);
+        if (owner && owner->keep) {
+            owner->kept.push_back({ptr, bytes});
+            owner->kept_bytes += bytes;
+        } else {
+            (void)hipFree(ptr);
+        }
         if (owner) owner->in_use -= bytes;
     }
     ptr = nullptr;
@@ -41,9 +46,40 @@ void DevBuf::release() {
     owner = nullptr;
 }
 
+void Allocator::drop_kept() {
+    for (const Kept& k : kept) (void)hipFree(k.ptr);
+    kept.clear();
+    kept_bytes = 0;
+}
+
+int sync_for_release(const Allocator& a, hipStream_t s) {
+    if (!a.keep) HIP_TRY(hipStreamSynchronize(s));
+    return HSPMM_OK;
+}
+
 int Allocator::alloc(DevBuf& b, size_t nbytes) {
     b.release();
     if (nbytes == 0) nbytes = 4;
+    if (keep) {
+        // the smallest kept buffer that holds nbytes and is at most twice
+        // that (plus a page)
+        size_t best = kept.size();
+        for (size_t i = 0; i < kept.size(); ++i)
+            if (kept[i].bytes >= nbytes && kept[i].bytes <= 2 * nbytes + 4096 &&
+                (best == kept.size() || kept[i].bytes < kept[best].bytes))
+                best = i;
+        if (best < kept.size()) {
+            b.ptr = kept[best].ptr;
+            b.bytes = kept[best].bytes;
+            b.owner = this;
+            kept_bytes -= b.bytes;
+            kept.erase(kept.begin() + (std::ptrdiff_t)best);
+            in_use += b.bytes;
+            peak = std::max(peak, in_use);
+            return HSPMM_OK;
+        }
+        if (limit && in_use + kept_bytes + nbytes > limit) drop_kept();
+    }
     if (limit && in_use + nbytes > limit)
         return fail(HSPMM_ERR_OOM, "plan exceeds max_workspace_bytes (" + std::to_string(limit) + ")");
     void* p = nullptr;

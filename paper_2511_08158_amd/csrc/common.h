@@ -72,13 +72,40 @@ struct DevBuf {
 };
 
 // Allocation accounting with an optional ceiling (max_workspace_bytes).
+// While a plan is built (`keep` set), released buffers are kept and handed
+// to later allocations of the build instead of being freed: hipFree waits
+// for the device, and all of the build's work is queued on one stream, so a
+// buffer reused in stream order needs no wait.  drop_kept() frees them.
 struct Allocator {
     uint64_t limit = 0;      // 0 = unlimited
     uint64_t in_use = 0;
     uint64_t peak = 0;
+    bool keep = false;
+    struct Kept {
+        void* ptr;
+        size_t bytes;
+    };
+    std::vector<Kept> kept;
+    uint64_t kept_bytes = 0;
     int alloc(DevBuf& b, size_t bytes);
     void free(DevBuf& b) { b.release(); }
+    void drop_kept();
 };
+
+// Keeps released buffers of `a` for reuse until it goes out of scope, then
+// frees them (one wait for the device instead of one per buffer).
+struct KeepBuffers {
+    Allocator& a;
+    explicit KeepBuffers(Allocator& x) : a(x) { a.keep = true; }
+    ~KeepBuffers() {
+        a.keep = false;
+        a.drop_kept();
+    }
+};
+
+// Wait for the stream before a buffer it uses is released, unless the
+// allocator keeps released buffers (stream-ordered reuse needs no wait).
+int sync_for_release(const Allocator& a, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // element types

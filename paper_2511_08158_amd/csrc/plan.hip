@@ -104,8 +104,18 @@ __global__ void k_canon_build(const int32_t* __restrict__ perm, const int32_t* _
 
 __global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
 
-__global__ void k_count(const int32_t* __restrict__ key, int64_t n, int32_t* __restrict__ cnt) {
-    GRID_STRIDE(i, n) atomicAdd(&cnt[key[i]], 1);
+// Row pointer of a list sorted by row (key[0..n) ascending, rows < nrows):
+// rp[r] = first t with key[t] >= r, rp[nrows] = n.  Thread t writes rp[r]
+// for the rows r in (key[t-1], key[t]]; the last thread also fills the
+// rows after the last key.
+__global__ void k_row_starts(const int32_t* __restrict__ key, int64_t n, int64_t nrows, int32_t* __restrict__ rp) {
+    GRID_STRIDE(t, n) {
+        const int32_t lo = t == 0 ? -1 : key[t - 1];
+        const int32_t hi = key[t];
+        for (int32_t r = lo + 1; r <= hi; ++r) rp[r] = (int32_t)t;
+        if (t == n - 1)
+            for (int64_t r = (int64_t)hi + 1; r <= nrows; ++r) rp[r] = (int32_t)n;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -187,6 +197,82 @@ __global__ void k_build_mask(const int32_t* __restrict__ blk_src, int64_t nblk_p
         uint32_t mk = 0;
         for (int i = 0; i < 16; ++i) mk |= (blk_src[pack_index(t, i, half)] >= 0 ? 1u : 0u) << i;
         blk_mask[t] = (uint16_t)mk;
+    }
+}
+
+// CSR-part work list, per row r of the sub-matrix: c[0] in the CSR-part,
+// c[1] its entries, c[2] its virtual rows, c[3] long (cut into segments),
+// c[4] its partial slots (all 0 outside the CSR-part); arrays of m each
+__global__ void k_wl_counts(const int32_t* __restrict__ rp, const uint8_t* __restrict__ cls, int64_t m, int br,
+                            int32_t seg, int32_t* __restrict__ c) {
+    GRID_STRIDE(r, m) {
+        const int32_t in = cls[r / br] ? 0 : 1;
+        const int32_t len = rp[r + 1] - rp[r];
+        const int32_t lng = in && len > seg ? 1 : 0;
+        const int32_t ns = lng ? (len + seg - 1) / seg : in;
+        c[r] = in;
+        c[m + r] = in ? len : 0;
+        c[2 * m + r] = ns;
+        c[3 * m + r] = lng;
+        c[4 * m + r] = lng ? ns : 0;
+    }
+}
+
+// Fill the CSR-part's rows and row pointer, the virtual rows (a long row's
+// segments in its place) and the long rows, from the counts' exclusive sums
+// x (same layout as c)
+__global__ void k_wl_fill(const int32_t* __restrict__ rp, const int32_t* __restrict__ c,
+                          const int32_t* __restrict__ x, int64_t m, int32_t seg, int64_t nrows_c,
+                          int32_t* __restrict__ rows, int32_t* __restrict__ cptr, int32_t* __restrict__ vs,
+                          int32_t* __restrict__ ve, int32_t* __restrict__ vo, int32_t* __restrict__ vrow,
+                          int32_t* __restrict__ lrow, int32_t* __restrict__ lfirst, int32_t* __restrict__ lcnt) {
+    GRID_STRIDE(r, m) {
+        if (!c[r]) continue;
+        const int32_t ri = x[r], base = x[m + r], len = c[m + r], v0 = x[2 * m + r];
+        rows[ri] = (int32_t)r;
+        cptr[ri] = base;
+        if (ri == nrows_c - 1) cptr[nrows_c] = base + len;
+        if (c[3 * m + r]) {
+            const int32_t li = x[3 * m + r], p0 = x[4 * m + r], ns = c[2 * m + r];
+            lrow[li] = (int32_t)r;
+            lfirst[li] = p0;
+            lcnt[li] = ns;
+            for (int32_t k = 0; k < ns; ++k) {
+                vs[v0 + k] = base + k * seg;
+                ve[v0 + k] = min(base + len, base + (k + 1) * seg);
+                vo[v0 + k] = -(p0 + k + 1);
+                vrow[v0 + k] = (int32_t)r;
+            }
+        } else {
+            vs[v0] = base;
+            ve[v0] = base + len;
+            vo[v0] = (int32_t)r;
+            vrow[v0] = (int32_t)r;
+        }
+    }
+}
+
+// sort key of virtual row v: its window, then 31 - floor(log2 len) (the
+// longest first; lengths 0 and 1 are class 0)
+__global__ void k_wl_keys(const int32_t* __restrict__ vs, const int32_t* __restrict__ ve, int64_t nv, int32_t window,
+                          uint32_t* __restrict__ key) {
+    GRID_STRIDE(v, nv) {
+        const uint32_t len = (uint32_t)(ve[v] - vs[v]);
+        const uint32_t cls = len > 1 ? 31u - (uint32_t)__clz((int)len) : 0u;
+        key[v] = ((uint32_t)(v / window) << 5) | (31u - cls);
+    }
+}
+
+__global__ void k_wl_gather(const int32_t* __restrict__ idx, int64_t nv, const int32_t* __restrict__ vs,
+                            const int32_t* __restrict__ ve, const int32_t* __restrict__ vo,
+                            const int32_t* __restrict__ vrow, int32_t* __restrict__ os, int32_t* __restrict__ oe,
+                            int32_t* __restrict__ oo, int32_t* __restrict__ orow) {
+    GRID_STRIDE(v, nv) {
+        const int32_t i = idx[v];
+        os[v] = vs[i];
+        oe[v] = ve[i];
+        oo[v] = vo[i];
+        orow[v] = vrow[i];
     }
 }
 
@@ -578,19 +664,18 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
         if (X.h_cls[q]) X.pred_bcsr += c.t_bcsr; else X.pred_csr += c.t_csr;
     }
 
-    // ---- CSR-part lists (host) ----
-    std::vector<int32_t> rows, cptr(1, 0);
-    int64_t acc = 0;
+    // ---- CSR-part lists ----
+    // Counts on the host from the row pointer it holds; the lists themselves
+    // are built on the device (no host arrays of the row count, no uploads).
+    int64_t nrows_c = 0, nnz_c = 0;
     for (int64_t q = 0; q < nrb; ++q) {
         if (X.h_cls[q]) continue;
-        for (int64_t r = q * br; r < std::min<int64_t>(m, q * br + br); ++r) {
-            rows.push_back((int32_t)r);
-            acc += h_rp[r + 1] - h_rp[r];
-            cptr.push_back((int32_t)acc);
-        }
+        const int64_t r1 = std::min<int64_t>(m, q * br + br);
+        nrows_c += r1 - q * br;
+        nnz_c += h_rp[r1] - h_rp[q * br];
     }
-    X.rows_csr = (int64_t)rows.size();
-    X.nnz_csr = acc;
+    X.rows_csr = nrows_c;
+    X.nnz_csr = nnz_c;
     // virtual rows: rows longer than `seg` entries are cut into segments whose
     // partial rows are summed in order by a second kernel.  A lane group walks
     // its segment in dependent rounds of gathers, so a long segment is a long
@@ -604,94 +689,100 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
         while (seg > 32 && X.nnz_csr < (int64_t)seg * kSegTarget) seg >>= 1;
     }
     X.seg = seg;
-    std::vector<int32_t> vs, ve, vo, vrow, lrow, lfirst, lcnt;
-    int64_t nparts = 0;
-    // one list in row order, a long row's segments in its place: each XCD
-    // takes a contiguous range of the list, so any cluster of long rows
-    // (all of them first, say) would load one XCD with most of the work;
-    // neighbouring rows also share gathered rows of B
-    for (int64_t r = 0; r < X.rows_csr; ++r) {
-        const int32_t lo = cptr[r], hi = cptr[r + 1];
-        if (hi - lo > seg) {
-            lrow.push_back(rows[r]);
-            lfirst.push_back((int32_t)nparts);
-            int32_t c = 0;
-            for (int32_t a = lo; a < hi; a += seg) {
-                vs.push_back(a);
-                ve.push_back(std::min(hi, a + seg));
-                vo.push_back((int32_t)(-(nparts + 1)));
-                vrow.push_back(rows[r]);
-                ++nparts;
-                ++c;
+    int64_t nv = 0, nlong = 0, nparts = 0;
+    int32_t maxlc = 0;
+    for (int64_t q = 0; q < nrb; ++q) {
+        if (X.h_cls[q]) continue;
+        for (int64_t r = q * br; r < std::min<int64_t>(m, q * br + br); ++r) {
+            const int32_t len = h_rp[r + 1] - h_rp[r];
+            if (len > seg) {
+                const int32_t ns = (len + seg - 1) / seg;
+                nv += ns;
+                nparts += ns;
+                ++nlong;
+                maxlc = std::max(maxlc, ns);
+            } else {
+                ++nv;
             }
-            lcnt.push_back(c);
-        } else {
-            vs.push_back(lo);
-            ve.push_back(hi);
-            vo.push_back(rows[r]);
-            vrow.push_back(rows[r]);
         }
     }
-    // A lane group takes one virtual row and a wave as many as it has lane
-    // groups, so a wave runs as long as its longest row.  Within windows of
-    // consecutive virtual rows, order them by length class floor(log2 len),
-    // longest first and stable: the rows of a wave then have lengths within
-    // a factor of two, rows of one class keep their order (and the B rows
-    // neighbouring rows share), and a window spans at most 1/32 of the list
-    // so every XCD's contiguous range keeps its share of long rows.
-    // Measured: power law FP16 fwd+bwd 2.05 -> 3.6 TFLOP/s, GCN 4.1 -> 4.5,
-    // block stencil unchanged (one length class); a sort over the whole
-    // list clusters the long rows on one XCD (3x slower), exact lengths
-    // break the stencil's row order (CSR-part 15 % slower).
+    X.n_vrows = nv;
+    X.n_long = nlong;
+    X.n_partials = nparts;
+    X.max_long_cnt = maxlc;
+    HSPMM_TRY(al.alloc(X.csr_rows, std::max<int64_t>(1, nrows_c) * 4));
+    HSPMM_TRY(al.alloc(X.csr_ptr, ((size_t)nrows_c + 1) * 4));
+    HSPMM_TRY(al.alloc(X.vr_start, std::max<int64_t>(1, nv) * 4));
+    HSPMM_TRY(al.alloc(X.vr_end, std::max<int64_t>(1, nv) * 4));
+    HSPMM_TRY(al.alloc(X.vr_out, std::max<int64_t>(1, nv) * 4));
+    HSPMM_TRY(al.alloc(X.vr_row, std::max<int64_t>(1, nv) * 4));
+    HSPMM_TRY(al.alloc(X.long_row, std::max<int64_t>(1, nlong) * 4));
+    HSPMM_TRY(al.alloc(X.long_first, std::max<int64_t>(1, nlong) * 4));
+    HSPMM_TRY(al.alloc(X.long_cnt, std::max<int64_t>(1, nlong) * 4));
+    HSPMM_TRY(fill_i32(X.csr_ptr.as<int32_t>(), 0, 1, s));
+    if (nrows_c > 0) {
+        // per row: in the CSR-part, its entries, virtual rows, long or not,
+        // partial slots; their exclusive sums place every list entry.  One
+        // list in row order, a long row's segments in its place: each XCD
+        // takes a contiguous range of the list, so any cluster of long rows
+        // (all of them first, say) would load one XCD with most of the work;
+        // neighbouring rows also share gathered rows of B
+        DevBuf d_cls, cnt, pre;
+        std::vector<uint8_t> cls8(X.h_cls.begin(), X.h_cls.end());
+        HSPMM_TRY(upload(al, d_cls, cls8, s));
+        HSPMM_TRY(al.alloc(cnt, (size_t)5 * m * 4));
+        HSPMM_TRY(al.alloc(pre, (size_t)5 * m * 4));
+        int32_t* c = cnt.as<int32_t>();
+        int32_t* x = pre.as<int32_t>();
+        hipLaunchKernelGGL(k_wl_counts, dim3(grid_for(m)), dim3(kThreads), 0, s, rp,
+                           static_cast<const uint8_t*>(d_cls.ptr), m, br, seg, c);
+        HIP_LAUNCH_CHECK();
+        for (int f = 0; f < 5; ++f) HSPMM_TRY(scan_exclusive_i32(c + f * m, x + f * m, m, nullptr, al, s));
+        DevBuf vs, ve, vo, vrow;
+        HSPMM_TRY(al.alloc(vs, std::max<int64_t>(1, nv) * 4));
+        HSPMM_TRY(al.alloc(ve, std::max<int64_t>(1, nv) * 4));
+        HSPMM_TRY(al.alloc(vo, std::max<int64_t>(1, nv) * 4));
+        HSPMM_TRY(al.alloc(vrow, std::max<int64_t>(1, nv) * 4));
+        hipLaunchKernelGGL(k_wl_fill, dim3(grid_for(m)), dim3(kThreads), 0, s, rp, c, x, m, seg, nrows_c,
+                           X.csr_rows.as<int32_t>(), X.csr_ptr.as<int32_t>(), vs.as<int32_t>(), ve.as<int32_t>(),
+                           vo.as<int32_t>(), vrow.as<int32_t>(), X.long_row.as<int32_t>(),
+                           X.long_first.as<int32_t>(), X.long_cnt.as<int32_t>());
+        HIP_LAUNCH_CHECK();
+        // A lane group takes one virtual row and a wave as many as it has
+        // lane groups, so a wave runs as long as its longest row.  Within
+        // windows of consecutive virtual rows, order them by length class
+        // floor(log2 len), longest first and stable: the rows of a wave then
+        // have lengths within a factor of two, rows of one class keep their
+        // order (and the B rows neighbouring rows share), and a window spans
+        // at most 1/32 of the list so every XCD's contiguous range keeps its
+        // share of long rows.  Measured: power law FP16 fwd+bwd 2.05 -> 3.6
+        // TFLOP/s, GCN 4.1 -> 4.5, block stencil unchanged (one length
+        // class); a sort over the whole list clusters the long rows on one
+        // XCD (3x slower), exact lengths break the stencil's row order
+        // (CSR-part 15 % slower).  One stable radix sort on the key
+        // (window, 31 - class).
 #ifndef HSPMM_SORT_WINDOW
 #define HSPMM_SORT_WINDOW 8192
 #endif
-    int64_t window = HSPMM_SORT_WINDOW;
-    while (window > 64 && window * 32 > (int64_t)vs.size()) window >>= 1;
-    if (window > 1) {
-        // a stable counting sort per window on the class, longest first
-        const size_t nv = vs.size();
-        std::vector<uint8_t> cls(nv);
-        for (size_t i = 0; i < nv; ++i) {
-            const uint32_t len = (uint32_t)(ve[i] - vs[i]);
-            cls[i] = len > 1 ? (uint8_t)(31 - __builtin_clz(len)) : 0;
-        }
-        std::vector<int32_t> idx(nv);
-        for (size_t w0 = 0; w0 < nv; w0 += (size_t)window) {
-            const size_t w1 = std::min(nv, w0 + (size_t)window);
-            size_t cnt[32] = {0}, off[32];
-            for (size_t i = w0; i < w1; ++i) ++cnt[cls[i]];
-            size_t at = w0;
-            for (int c = 31; c >= 0; --c) {
-                off[c] = at;
-                at += cnt[c];
-            }
-            for (size_t i = w0; i < w1; ++i) idx[off[cls[i]]++] = (int32_t)i;
-        }
-        auto apply = [&](std::vector<int32_t>& v) {
-            std::vector<int32_t> t(v.size());
-            for (size_t i = 0; i < idx.size(); ++i) t[i] = v[idx[i]];
-            v.swap(t);
-        };
-        apply(vs);
-        apply(ve);
-        apply(vo);
-        apply(vrow);
+        int64_t window = HSPMM_SORT_WINDOW;
+        while (window > 64 && window * 32 > nv) window >>= 1;
+        DevBuf keys, idx, ktmp, itmp;
+        HSPMM_TRY(al.alloc(keys, (size_t)nv * 4));
+        HSPMM_TRY(al.alloc(idx, (size_t)nv * 4));
+        HSPMM_TRY(al.alloc(ktmp, (size_t)nv * 4));
+        HSPMM_TRY(al.alloc(itmp, (size_t)nv * 4));
+        HSPMM_TRY(iota_i32(idx.as<int32_t>(), nv, s));
+        hipLaunchKernelGGL(k_wl_keys, dim3(grid_for(nv)), dim3(kThreads), 0, s, vs.as<int32_t>(), ve.as<int32_t>(),
+                           nv, (int32_t)window, keys.as<uint32_t>());
+        HIP_LAUNCH_CHECK();
+        HSPMM_TRY(radix_sort_pairs(keys.as<uint32_t>(), idx.as<int32_t>(), ktmp.as<uint32_t>(),
+                                   itmp.as<int32_t>(), nv, bits_for((nv - 1) / window) + 5, al, s));
+        hipLaunchKernelGGL(k_wl_gather, dim3(grid_for(nv)), dim3(kThreads), 0, s, idx.as<int32_t>(), nv,
+                           vs.as<int32_t>(), ve.as<int32_t>(), vo.as<int32_t>(), vrow.as<int32_t>(),
+                           X.vr_start.as<int32_t>(), X.vr_end.as<int32_t>(), X.vr_out.as<int32_t>(),
+                           X.vr_row.as<int32_t>());
+        HIP_LAUNCH_CHECK();
     }
-    X.n_vrows = (int64_t)vs.size();
-    X.n_long = (int64_t)lrow.size();
-    X.n_partials = nparts;
-    X.max_long_cnt = lcnt.empty() ? 0 : *std::max_element(lcnt.begin(), lcnt.end());
-
-    HSPMM_TRY(upload(al, X.csr_rows, rows, s));
-    HSPMM_TRY(upload(al, X.csr_ptr, cptr, s));
-    HSPMM_TRY(upload(al, X.vr_start, vs, s));
-    HSPMM_TRY(upload(al, X.vr_end, ve, s));
-    HSPMM_TRY(upload(al, X.vr_out, vo, s));
-    HSPMM_TRY(upload(al, X.vr_row, vrow, s));
-    HSPMM_TRY(upload(al, X.long_row, lrow, s));
-    HSPMM_TRY(upload(al, X.long_first, lfirst, s));
-    HSPMM_TRY(upload(al, X.long_cnt, lcnt, s));
     HSPMM_TRY(al.alloc(X.csr_col, std::max<int64_t>(1, X.nnz_csr) * 4));
     HSPMM_TRY(al.alloc(X.csr_src, std::max<int64_t>(1, X.nnz_csr) * 4));
     HSPMM_TRY(al.alloc(X.csr_val, std::max<int64_t>(1, X.nnz_csr) * dtype_size(X.ct)));
@@ -759,7 +850,7 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
                                X.rb_bcsr, X.ct == HSPMM_F64, X.chunk_base.as<int32_t>(),
                                static_cast<uint16_t*>(X.chunk_mask.ptr));
             HIP_LAUNCH_CHECK();
-            HIP_TRY(hipStreamSynchronize(s));
+            HSPMM_TRY(sync_for_release(al, s));
             al.free(mask);
         }
         if (&X == &p.T && !half && X.nblk_pad > 0) {
@@ -770,10 +861,12 @@ int build_sub(Plan& p, SubPlan& X, const int32_t* rp, const int32_t* col, const 
                                static_cast<uint16_t*>(X.tile_mask.ptr));
             HIP_LAUNCH_CHECK();
         }
-        HIP_TRY(hipStreamSynchronize(s));
+        HSPMM_TRY(sync_for_release(al, s));
         al.free(d_slot);
         HSPMM_TRY(build_sub_groups(p, X, s));
     }
+    // host vectors of this function were copied to the device: wait before
+    // they go out of scope (also the buffers below, unless kept for reuse)
     HIP_TRY(hipStreamSynchronize(s));
     al.free(ord);
     al.free(hd);
@@ -847,7 +940,7 @@ int pack_values(Plan& p, const void* vals, int vals_dtype, hipStream_t s) {
     HSPMM_TRY(canonical_values(p, vals, vals_dtype, vb, s));
     HSPMM_TRY(pack_a_like(p, p.A, vb.as<double>(), s));
     if (p.has_T) HSPMM_TRY(pack_sub_any(p, p.T, vb.as<double>(), p.compute, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HSPMM_TRY(sync_for_release(p.al, s));
     p.al.free(vb);
     return HSPMM_OK;
 }
@@ -900,6 +993,9 @@ int time_whole_part(Plan& p, const SubPlan& like, int split, const int32_t* rp, 
 int build_plan(Plan& p, const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int vals_dtype,
                hipStream_t s) {
     Allocator& al = p.al;
+    // the build's temporaries are reused in stream order, and freed at its
+    // end (constructed before them, so destroyed after them)
+    KeepBuffers keep(al);
     const int64_t m = p.m, nin = p.nnz_in;
 
     DevBuf flags;
@@ -976,16 +1072,15 @@ int build_plan(Plan& p, const int32_t* row_ptr, const int32_t* col_idx, const vo
         HIP_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, p.seg.as<int32_t>() + nc, (int32_t)nin);
         HIP_LAUNCH_CHECK();
-        // canonical row pointer from per-row counts
-        DevBuf cnt;
-        HSPMM_TRY(al.alloc(cnt, ((size_t)m + 1) * 4));
-        HIP_TRY(hipMemsetAsync(cnt.ptr, 0, ((size_t)m + 1) * 4, s));
-        hipLaunchKernelGGL(k_count, dim3(grid_for(nc)), dim3(kThreads), 0, s, p.row_of.as<int32_t>(), (int64_t)nc,
-                           cnt.as<int32_t>());
-        HIP_LAUNCH_CHECK();
-        HSPMM_TRY(scan_exclusive_i32(cnt.as<int32_t>(), crp.as<int32_t>(), m + 1, nullptr, al, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        al.free(cnt);
+        // canonical row pointer from the run starts of the (sorted) rows
+        if (nc > 0) {
+            hipLaunchKernelGGL(k_row_starts, dim3(grid_for(nc)), dim3(kThreads), 0, s, p.row_of.as<int32_t>(),
+                               (int64_t)nc, m, crp.as<int32_t>());
+            HIP_LAUNCH_CHECK();
+        } else {
+            HSPMM_TRY(fill_i32(crp.as<int32_t>(), 0, m + 1, s));
+        }
+        HSPMM_TRY(sync_for_release(al, s));
         al.free(head);
         al.free(hx);
         al.free(total);
@@ -1028,7 +1123,7 @@ int build_plan(Plan& p, const int32_t* row_ptr, const int32_t* col_idx, const vo
         T.br = p.br;
         T.kc = 4;
         T.scaled = false;
-        DevBuf ord, keys, ktmp, vtmp, tcol, trow, trp, cnt;
+        DevBuf ord, keys, ktmp, vtmp, tcol, trow, trp;
         const int64_t nc = p.nnz;
         HSPMM_TRY(al.alloc(ord, std::max<int64_t>(1, nc) * 4));
         HSPMM_TRY(al.alloc(keys, std::max<int64_t>(1, nc) * 4));
@@ -1048,18 +1143,20 @@ int build_plan(Plan& p, const int32_t* row_ptr, const int32_t* col_idx, const vo
         HSPMM_TRY(al.alloc(tcol, std::max<int64_t>(1, nc) * 4));
         HSPMM_TRY(al.alloc(trow, std::max<int64_t>(1, nc) * 4));
         HSPMM_TRY(al.alloc(trp, ((size_t)p.k + 1) * 4));
-        HSPMM_TRY(al.alloc(cnt, ((size_t)p.k + 1) * 4));
-        HIP_TRY(hipMemsetAsync(cnt.ptr, 0, ((size_t)p.k + 1) * 4, s));
         if (nc > 0) {
             hipLaunchKernelGGL(k_transpose_fill, dim3(grid_for(nc)), dim3(kThreads), 0, s, ord.as<int32_t>(),
                                p.row_of.as<int32_t>(), ccol.as<int32_t>(), nc, tcol.as<int32_t>(),
                                trow.as<int32_t>());
             HIP_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_count, dim3(grid_for(nc)), dim3(kThreads), 0, s, trow.as<int32_t>(), nc,
-                               cnt.as<int32_t>());
+            // trow is sorted (the entries in column order): A^T's row
+            // pointer from its run starts, not from per-row counters (the
+            // atomics of a counter pass collide on every long row)
+            hipLaunchKernelGGL(k_row_starts, dim3(grid_for(nc)), dim3(kThreads), 0, s, trow.as<int32_t>(), nc,
+                               p.k, trp.as<int32_t>());
             HIP_LAUNCH_CHECK();
+        } else {
+            HSPMM_TRY(fill_i32(trp.as<int32_t>(), 0, p.k + 1, s));
         }
-        HSPMM_TRY(scan_exclusive_i32(cnt.as<int32_t>(), trp.as<int32_t>(), p.k + 1, nullptr, al, s));
         HSPMM_TRY(build_sub(p, T, trp.as<int32_t>(), tcol.as<int32_t>(), trow.as<int32_t>(), ord.as<int32_t>(), s));
         HIP_TRY(hipStreamSynchronize(s));
         p.has_T = true;

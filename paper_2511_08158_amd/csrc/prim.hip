@@ -189,8 +189,8 @@ int scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* tota
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, out, n,
                        part.as<int32_t>());
     HIP_LAUNCH_CHECK();
-    // `part` is released when this returns; the stream is synchronised first
-    HIP_TRY(hipStreamSynchronize(s));
+    // `part` is released when this returns (after the stream's work on it)
+    HSPMM_TRY(sync_for_release(al, s));
     al.free(part);
     return HSPMM_OK;
 }
@@ -223,7 +223,7 @@ int radix_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys_tmp, int32_t*
         HIP_TRY(hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(vals, va, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     }
-    HIP_TRY(hipStreamSynchronize(s));
+    HSPMM_TRY(sync_for_release(al, s));
     al.free(hist);
     return HSPMM_OK;
 }
