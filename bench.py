@@ -254,11 +254,20 @@ def gcn_train(args):
     W1 = torch.tensor(w1, device=dev, dtype=torch.float32, requires_grad=True)
     W2 = torch.tensor(w2, device=dev, dtype=torch.float32, requires_grad=True)
     vals = torch.tensor(a.vals, device=dev, dtype=torch.float32)
+    rp_d = torch.tensor(a.row_ptr, device=dev, dtype=torch.int32)
+    ci_d = torch.tensor(a.col_idx, device=dev, dtype=torch.int32)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan = hs.Plan(a.row_ptr, a.col_idx, vals, (a.m, a.k), compute=torch.float32, backward=True, n_hint=hidden)
-    torch.cuda.synchronize()
-    plan_ms = (time.perf_counter() - t0) * 1e3
+    # the plan from the graph's CSR pattern resident on the device (the
+    # preprocessing the paper times, Sec. 4.5), twice: the first build in a
+    # process also pays first-use costs of the runtime
+    plan_ms = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        plan = hs.Plan(rp_d, ci_d, vals, (a.m, a.k), compute=torch.float32, backward=True, n_hint=hidden)
+        torch.cuda.synchronize()
+        plan_ms.append((time.perf_counter() - t0) * 1e3)
+    plan_ms_first = plan_ms[0]
+    plan_ms = plan_ms[-1]
     opt = torch.optim.SGD([W1, W2], lr=0.5)
 
     def forward():
@@ -321,7 +330,8 @@ def gcn_train(args):
         "nodes": a.m, "nnz": a.nnz, "features": x.shape[1], "hidden": hidden, "classes": classes,
         "epochs_timed": args.epochs, "epoch_ms": round(epoch_ms, 3),
         "sparse_ms_per_epoch": round(sp_ms, 3), "sparse_share": round(sp_ms / epoch_ms, 3),
-        "plan_ms": round(plan_ms, 1), "plan_share_100_epochs": round(plan_ms / (plan_ms + 100 * epoch_ms), 4),
+        "plan_ms": round(plan_ms, 1), "plan_ms_first_build": round(plan_ms_first, 1),
+        "plan_share_100_epochs": round(plan_ms / (plan_ms + 100 * epoch_ms), 4),
         "split": {k: plan.info()[k] for k in ("rows_csr", "rb_bcsr")},
         "loss_first": round(float(loss0), 5), "loss_first_fp64": round(ref_loss, 5),
         "loss_last": round(float(losses[-1]), 5),
@@ -400,11 +410,18 @@ def main():
     vals = torch.tensor(a.vals, device=dev)
     B = torch.tensor(b, device=dev).to(tdtype)
     dC = torch.tensor(g, device=dev, dtype=torch.float32)
+    # the input CSR pattern resident on the device, as the values are: the
+    # plan time is the format build alone (the upload is reported beside it)
+    torch.cuda.synchronize()
+    t_up = time.perf_counter()
+    rp_d = torch.tensor(a.row_ptr, device=dev, dtype=torch.int32)
+    ci_d = torch.tensor(a.col_idx, device=dev, dtype=torch.int32)
+    torch.cuda.synchronize()
+    upload_ms = (time.perf_counter() - t_up) * 1e3
 
     def make(split):
         t0 = time.perf_counter()
-        p = hs.Plan(a.row_ptr, a.col_idx, vals, (a.m, a.k), compute=tdtype, split=split,
-                    backward=True, n_hint=n)
+        p = hs.Plan(rp_d, ci_d, vals, (a.m, a.k), compute=tdtype, split=split, backward=True, n_hint=n)
         torch.cuda.synchronize()
         return p, (time.perf_counter() - t0) * 1e3
 
@@ -678,6 +695,7 @@ def main():
         "error_ok": None if err is None else all(v <= tol for v in err.values()),
         "kernels_us": rnd(kc),
         "plan_ms": round(results["auto"]["plan_ms"], 1),
+        "csr_upload_ms": round(upload_ms, 1),
         "split": {k: results["auto"]["info"][k] for k in ("rows_csr", "rb_bcsr", "nblk", "fill")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
