@@ -70,7 +70,5 @@ extern "C" int hybrid_spmm_run_noalloc(hspmm_plan_t h, int64_t n, const void* B,
         ws.bytes = kScratchBytes;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    HSPMM_TRY(launch_forward(p, p.A, n, B, ldb, C, ldc, s, nullptr, &ws));
-    mark_stream_noalloc(p, s);
-    return HSPMM_OK;
+    return launch_forward(p, p.A, n, B, ldb, C, ldc, s, nullptr, &ws);
 }

@@ -104,16 +104,6 @@ struct Plan {
     std::vector<DevBuf> retired;
     double plan_ms = 0.0;
 
-    // an event recorded after the last call on each stream the plan was used
-    // on: destroy waits for these instead of the whole device
-    struct StreamMark {
-        hipStream_t s;
-        hipEvent_t e;
-    };
-    std::vector<StreamMark> marks;
-    bool marks_overflow = false;  // more streams than kMaxMarks were used
-    static constexpr size_t kMaxMarks = 16;
-
     // side stream of the backward: dA = SDDMM runs on it concurrently with
     // dB = A^T dC, forked from and joined back to the caller's stream by
     // events (default stream priority)
@@ -144,9 +134,6 @@ int launch_forward(Plan& p, SubPlan& X, int64_t n, const void* B, int64_t ldb, v
                    hipStream_t s, LaunchQuery* q = nullptr, const Workspace* ext = nullptr);
 // bytes of split-row scratch a forward product of X at width n needs
 size_t forward_scratch_bytes(const SubPlan& X, int64_t n);
-// like mark_stream, but never creates an event: a stream without one makes
-// destroy wait for the whole device instead
-void mark_stream_noalloc(Plan& p, hipStream_t s);
 // SDDMM on A's pattern: dA_canon[c] (or dA_in[e] via canon_of_orig)
 int launch_sddmm(Plan& p, int64_t n, const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dA,
                  hipStream_t s, DevBuf* ws);
@@ -154,10 +141,6 @@ int ensure_ws(Plan& p, size_t bytes);
 // grow `b` to at least `bytes` without waiting for the device: the old
 // buffer goes to p.retired
 int grow_buf(Plan& p, DevBuf& b, size_t bytes);
-// record that work of the plan was queued on stream s
-int mark_stream(Plan& p, hipStream_t s);
-// wait for the plan's queued work (the events of mark_stream)
-void wait_plan(Plan& p);
 
 // Both gradients from one pass over A^T's BCSR-part (FP32 / FP64, A^T all
 // BCSR, n within one column panel, 16-byte rows): bwd_fusable says whether
