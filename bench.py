@@ -82,6 +82,8 @@ def parse():
                     help="skip the same step in the other compute precisions (stencil only)")
     ap.add_argument("--graded-only", action="store_true",
                     help="only the W warm-up and K timed cold steps of the hybrid plan (for profiling)")
+    ap.add_argument("--dtype", default=None, choices=["f64", "f32", "f16", "bf16"],
+                    help="with --graded-only: the step in this compute precision (default: the workload's)")
     return ap.parse_args()
 
 
@@ -406,12 +408,19 @@ def main():
 
     dev = torch.device("cuda:0")
     a, b, dt, wname = workload(args.workload)
-    tdtype = {"f32": torch.float32, "f16": torch.float16}[dt]
+    if args.dtype is not None:
+        if not args.graded_only:
+            print("--dtype applies to --graded-only runs", file=sys.stderr)
+            sys.exit(2)
+        dt = args.dtype
+    tdtype = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dt]
+    # outputs and dC: FP64 for an FP64 step, FP32 otherwise
+    odt = torch.float64 if dt == "f64" else torch.float32
     n = b.shape[1]
     g = gen.dense(0, gen.GRAD, a.m, n)
     vals = torch.tensor(a.vals, device=dev)
     B = torch.tensor(b, device=dev).to(tdtype)
-    dC = torch.tensor(g, device=dev, dtype=torch.float32)
+    dC = torch.tensor(g, device=dev, dtype=odt)
     # the input CSR pattern resident on the device, as the values are: the
     # plan time is the format build alone (the upload is reported beside it)
     torch.cuda.synchronize()
@@ -577,10 +586,10 @@ def main():
         # the graded measurement alone (the profiled command): W warm-up and
         # K timed cold steps of the hybrid plan
         plan, _ = make("auto")
-        cs = cold_steps(plan, args.steps, args.warmup, per_kernel=False)
-        ck = cold_steps(plan, args.steps, 2, per_kernel=True)
+        cs = cold_steps(plan, args.steps, args.warmup, per_kernel=False, out_dtype=odt)
+        ck = cold_steps(plan, args.steps, 2, per_kernel=True, out_dtype=odt)
         t = float(np.median(cs["step_us"])) * 1e-6
-        print(json.dumps({"graded_only": True, "workload": wname, "steps": args.steps, "warmup": args.warmup,
+        print(json.dumps({"graded_only": True, "workload": wname, "dtype": dt, "steps": args.steps, "warmup": args.warmup,
                           "value": round(flops / t / 1e9, 2), "ms_per_step": round(t * 1e3, 5),
                           "kernels_us_cold_mean": {k: round(float(v.mean()), 2) for k, v in ck["kernels"].items()}}),
               flush=True)
