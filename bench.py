@@ -84,7 +84,10 @@ def parse():
                     help="only the W warm-up and K timed cold steps of the hybrid plan (for profiling)")
     ap.add_argument("--dtype", default=None, choices=["f64", "f32", "f16", "bf16"],
                     help="with --graded-only: the step in this compute precision (default: the workload's)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.dtype is not None and not args.graded_only:
+        ap.error("--dtype applies to --graded-only runs")
+    return args
 
 
 # The paper's own figures (Apple M4 Pro CPU, SuiteSparse matrices, N = 32,
@@ -409,9 +412,6 @@ def main():
     dev = torch.device("cuda:0")
     a, b, dt, wname = workload(args.workload)
     if args.dtype is not None:
-        if not args.graded_only:
-            print("--dtype applies to --graded-only runs", file=sys.stderr)
-            sys.exit(2)
         dt = args.dtype
     tdtype = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dt]
     # outputs and dC: FP64 for an FP64 step, FP32 otherwise

@@ -1,5 +1,6 @@
 """bench.py's command-line contract that needs no GPU: asking for more than
-one GPU ends with a message and exit status 2 before any device work."""
+one GPU, or a precision outside the graded-only measurement, ends with a
+message and exit status 2 before any device work."""
 import subprocess
 import sys
 from pathlib import Path
@@ -12,4 +13,12 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_dtype_needs_graded_only():
+    r = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--dtype", "f64"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--graded-only" in r.stderr
     assert r.stdout.strip() == ""
