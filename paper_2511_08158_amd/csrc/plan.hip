@@ -105,16 +105,22 @@ __global__ void k_canon_build(const int32_t* __restrict__ perm, const int32_t* _
 __global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
 
 // Row pointer of a list sorted by row (key[0..n) ascending, rows < nrows):
-// rp[r] = first t with key[t] >= r, rp[nrows] = n.  Thread t writes rp[r]
-// for the rows r in (key[t-1], key[t]]; the last thread also fills the
-// rows after the last key.
+// rp[r] = the first t with key[t] >= r (n if none), so rp[nrows] = n.  One
+// thread per row finds it by binary search: a long stretch of empty rows
+// costs no more than any other rows (writing the rows between consecutive
+// keys from the key's thread would leave one thread all of them).
 __global__ void k_row_starts(const int32_t* __restrict__ key, int64_t n, int64_t nrows, int32_t* __restrict__ rp) {
-    GRID_STRIDE(t, n) {
-        const int32_t lo = t == 0 ? -1 : key[t - 1];
-        const int32_t hi = key[t];
-        for (int32_t r = lo + 1; r <= hi; ++r) rp[r] = (int32_t)t;
-        if (t == n - 1)
-            for (int64_t r = (int64_t)hi + 1; r <= nrows; ++r) rp[r] = (int32_t)n;
+    GRID_STRIDE(r, nrows + 1) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (key[mid] < r) {
+                lo = mid + 1;
+            } else {
+                hi = mid;
+            }
+        }
+        rp[r] = (int32_t)lo;
     }
 }
 
@@ -1074,7 +1080,7 @@ int build_plan(Plan& p, const int32_t* row_ptr, const int32_t* col_idx, const vo
         HIP_LAUNCH_CHECK();
         // canonical row pointer from the run starts of the (sorted) rows
         if (nc > 0) {
-            hipLaunchKernelGGL(k_row_starts, dim3(grid_for(nc)), dim3(kThreads), 0, s, p.row_of.as<int32_t>(),
+            hipLaunchKernelGGL(k_row_starts, dim3(grid_for(m + 1)), dim3(kThreads), 0, s, p.row_of.as<int32_t>(),
                                (int64_t)nc, m, crp.as<int32_t>());
             HIP_LAUNCH_CHECK();
         } else {
@@ -1151,7 +1157,7 @@ int build_plan(Plan& p, const int32_t* row_ptr, const int32_t* col_idx, const vo
             // trow is sorted (the entries in column order): A^T's row
             // pointer from its run starts, not from per-row counters (the
             // atomics of a counter pass collide on every long row)
-            hipLaunchKernelGGL(k_row_starts, dim3(grid_for(nc)), dim3(kThreads), 0, s, trow.as<int32_t>(), nc,
+            hipLaunchKernelGGL(k_row_starts, dim3(grid_for(p.k + 1)), dim3(kThreads), 0, s, trow.as<int32_t>(), nc,
                                p.k, trp.as<int32_t>());
             HIP_LAUNCH_CHECK();
         } else {
