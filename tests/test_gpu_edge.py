@@ -1,7 +1,8 @@
 """Edge cases on the GPU: empty row blocks in the FP16/BF16 matrix-core
 forms, the Eq. 1 boundary the library solves against the oracle's Eq. 1, the
 FP16/BF16 SDDMM on a dC slab far below FP16's range, the autograd function
-with several forward calls on one plan, and the binding's operand checks."""
+with several forward calls on one plan, the binding's operand checks, and
+row pointers across long stretches of empty rows."""
 import gc
 
 import numpy as np
@@ -250,3 +251,35 @@ def test_eq1_boundary_from_measured_throughputs(dtype):
     torch.cuda.synchronize()
     assert oracle.rel_err(C.double().cpu().numpy(),
                           oracle.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, b)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("split", ["auto", "csr", "bcsr"])
+def test_long_stretches_of_empty_rows(split):
+    """Entries in the first and last rows only, in 12 of 60,000 columns:
+    A's row pointer and A^T's have tens of thousands of empty rows in a
+    row, at the start, in the middle and at the end of the key lists.
+    Forward, dB and dA against the oracle."""
+    print(f"empty stretches split={split}", flush=True)
+    g = np.random.default_rng(31)
+    m, k, n = 5000, 60000, 64
+    cols = np.array([0, 1, 2, 3, 17, 18, 30000, 30001, 59990, 59995, 59998, 59999])
+    r = np.concatenate([np.zeros(cols.size, np.int64), np.full(cols.size, m - 1)])
+    c = np.concatenate([cols, cols])
+    a = gen.csr_from_coo(m, k, r, c, g.standard_normal(r.size))
+    plan = make_plan(hs, a, torch.float32, split, backward=True)
+    B = g.standard_normal((k, n))
+    G = g.standard_normal((m, n))
+    Bd, Gd = to_dev(B, torch.float32), to_dev(G, torch.float32)
+    C = plan.run(Bd)
+    dB, dA = plan.backward(Bd, Gd)
+    torch.cuda.synchronize()
+    assert oracle.rel_err(C.double().cpu().numpy(), oracle.spmm(a.m, a.k, a.row_ptr, a.col_idx, a.vals, B)) <= TOL[torch.float32]
+    assert oracle.rel_err(dB.double().cpu().numpy(),
+                          oracle.spmm_t(a.m, a.k, a.row_ptr, a.col_idx, a.vals, G)) <= TOL[torch.float32]
+    assert oracle.rel_err(dA.double().cpu().numpy(), oracle.sddmm(a.m, a.k, a.row_ptr, a.col_idx, G, B)) <= TOL[torch.float32]
+    # the rows of C and dB without entries are exactly zero
+    Ch, dBh = C.cpu().numpy(), dB.cpu().numpy()
+    assert not Ch[1:m - 1].any()
+    keep = np.ones(k, bool)
+    keep[cols] = False
+    assert not dBh[keep].any()
