@@ -1,8 +1,9 @@
 """Edge cases on the GPU: empty row blocks in the FP16/BF16 matrix-core
 forms, the Eq. 1 boundary the library solves against the oracle's Eq. 1, the
 FP16/BF16 SDDMM on a dC slab far below FP16's range, the autograd function
-with several forward calls on one plan, the binding's operand checks, and
-row pointers across long stretches of empty rows."""
+with several forward calls on one plan, the binding's operand checks, row
+pointers across long stretches of empty rows, and the backward of a matrix
+without entries and at n = 0."""
 import gc
 
 import numpy as np
@@ -283,3 +284,33 @@ def test_long_stretches_of_empty_rows(split):
     keep = np.ones(k, bool)
     keep[cols] = False
     assert not dBh[keep].any()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_backward_degenerate_shapes(dtype):
+    """A matrix without entries: C and dB are all zeros (written, not left
+    as they were), dA is empty.  n = 0: C and dB are empty and every dA
+    entry is the empty dot product, 0."""
+    print(f"degenerate backward dtype={dtype}", flush=True)
+    od = torch.float64 if dtype == torch.float64 else torch.float32
+    z = gen.csr_from_coo(40, 30, np.zeros(0, int), np.zeros(0, int))
+    plan = make_plan(hs, z, dtype, "auto", backward=True)
+    g = np.random.default_rng(5)
+    Bd = to_dev(g.standard_normal((30, 8)), dtype)
+    Gd = to_dev(g.standard_normal((40, 8)), od)
+    C = torch.full((40, 8), 7.0, dtype=od, device=Bd.device)
+    plan.run(Bd, out=C)
+    dB, dA = plan.backward(Bd, Gd)
+    torch.cuda.synchronize()
+    assert not C.cpu().numpy().any()
+    assert dB.shape == (30, 8) and not dB.cpu().numpy().any()
+    assert dA.numel() == 0
+    a = gen.random_csr(6, 70, 50, 0.1)
+    plan = make_plan(hs, a, dtype, "auto", backward=True)
+    B0 = torch.zeros((50, 0), dtype=dtype, device=Bd.device)
+    G0 = torch.zeros((70, 0), dtype=od, device=Bd.device)
+    C0 = plan.run(B0)
+    dB0, dA0 = plan.backward(B0, G0)
+    torch.cuda.synchronize()
+    assert C0.shape == (70, 0) and dB0.shape == (50, 0)
+    assert dA0.shape == (a.nnz,) and not dA0.cpu().numpy().any()
